@@ -1,0 +1,93 @@
+"""The CPU oracle, pinned to facts outside itself (CPU only)."""
+
+import os
+import shutil
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from pins import pin_failures, workload_invariant_failures
+from golden_io import load_examples
+
+
+def test_golden_examples_parse():
+    exs = load_examples()
+    assert len(exs) >= 10
+    for ex in exs:
+        assert ex.cite and len(ex.counts) == len(ex.patterns)
+        assert sum(ex.counts) == len(ex.matches)
+
+
+def test_oracle_meets_every_pin():
+    assert pin_failures(oracle._load()) == []
+
+
+def test_empty_pattern_rejected():
+    with pytest.raises(ValueError):
+        oracle.match(b"abc", [b"a", b""])
+
+
+def test_empty_dictionary():
+    off, ids, counts, total = oracle.match(b"abc", [])
+    assert total == 0 and off.size == 0 and counts.size == 0
+
+
+def test_thread_count_does_not_change_result():
+    pats, text, _ = synth.make_workload("tiny", n_bytes=256 << 10)
+    ref = oracle.match(text, pats, bucketed=True, threads=1)
+    for t in (2, 5, 8):
+        got = oracle.match(text, pats, bucketed=True, threads=t)
+        assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+        assert np.array_equal(ref[2], got[2]) and ref[3] == got[3]
+
+
+@pytest.mark.parametrize("name,n_bytes", [("tiny", None), ("medium", 4 << 20), ("large", 2 << 20)])
+def test_oracle_invariants_on_workloads(name, n_bytes):
+    pats, text, plants = synth.make_workload(name, n_bytes=n_bytes)
+    off, ids, counts, total = oracle.match(text, pats, bucketed=True)
+    assert total >= len(plants) > 0
+    assert workload_invariant_failures(text, pats, plants, off, ids, counts, total) == []
+
+
+def test_plain_equals_bucketed_on_workload_slices():
+    for name, nb in (("tiny", None), ("medium", 1 << 20), ("large", 96 << 10)):
+        pats, text, _ = synth.make_workload(name, n_bytes=nb)
+        a = oracle.match(text, pats, bucketed=False)
+        b = oracle.match(text, pats, bucketed=True)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[2], b[2]) and a[3] == b[3]
+
+
+# Plausible mistakes, planted in a copy of the oracle source; the pins must
+# catch every one.  (old text, new text) pairs.
+MUTANTS = {
+    "fit-off-by-one": ("if (len > pb->n_text - i) return 0;", "if (len >= pb->n_text - i) return 0;"),
+    "short-compare": ("(size_t)len) == 0;", "(size_t)len - 1) == 0;"),
+    "drop-last-pattern": ("for (uint32_t j = 0; j < pb->n_pat; j++)\n                if (occurs_at",
+                          "for (uint32_t j = 0; j + 1 < pb->n_pat; j++)\n                if (occurs_at"),
+    "bucket-drops-last": ("k < pb->bucket_at[first + 1]; k++", "k + 1 < pb->bucket_at[first + 1]; k++"),
+    "count-not-accumulated": ("if (r->counts) r->counts[j] += 1;", "if (r->counts) r->counts[j] = 1;"),
+    "range-order-shift": ("rs[t].out_base = total;\n        total += rs[t].found;",
+                          "total += rs[t].found;\n        rs[t].out_base = total;"),
+    "range-split-gap": ("rs[t].hi = n_text * (uint64_t)(t + 1) / (uint64_t)threads;",
+                        "rs[t].hi = n_text * (uint64_t)(t + 1) / (uint64_t)threads - (t + 1 < threads);"),
+    "one-match-per-offset": ("if (occurs_at(pb, i, j)) record(r, i, j);\n            }",
+                             "if (occurs_at(pb, i, j)) { record(r, i, j); break; }\n            }"),
+    "reversed-compare": ("memcmp(pb->text + i, pb->pat_bytes + pb->pat_off[j], (size_t)len) == 0",
+                         "memcmp(pb->text + i + 1, pb->pat_bytes + pb->pat_off[j], (size_t)len) == 0"),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(mutant, tmp_path):
+    src = Path(oracle.__file__).resolve().parent / "glop_oracle.c"
+    text = src.read_text()
+    old, new = MUTANTS[mutant]
+    assert text.count(old) == 1, f"mutation site for {mutant} not found exactly once"
+    mut_src = tmp_path / "mutant.c"
+    mut_src.write_text(text.replace(old, new))
+    lib = oracle._bind(oracle.compile_oracle(mut_src, tmp_path / "libmutant.so"))
+    assert pin_failures(lib, n_random=60) != [], f"no pin detects mutant {mutant}"
