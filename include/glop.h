@@ -1,0 +1,225 @@
+/*
+ * glop.h -- exact multi-pattern matching of a pattern dictionary against log
+ * text on one MI355X (gfx950), after the failureless-trie method of
+ * "GLoP: Enabling Massively Parallel Incident Response Through GPU Log
+ * Processing" (arXiv 1704.02278).
+ *
+ * The problem (Section 1): rules (byte patterns) and logs (text) go in; out
+ * come the number of suspicious events and their locations.  The method
+ * (Sections 4-5) first builds a state machine from the patterns -- here a
+ * failureless trie, i.e. goto edges only -- and then starts one walk of that
+ * trie at every byte offset of the text; a walk follows the text while it
+ * spells a pattern prefix and ends at the first byte with no edge.  Every
+ * overlapping occurrence is therefore found:
+ *
+ *   M = { (i, j) : i + |p_j| <= len and text[i .. i+|p_j|) == p_j }
+ *
+ * reported as glop_match_t records sorted by ascending offset, then ascending
+ * pattern id, plus per-pattern counts C[j] = #{ i : (i, j) in M }.
+ *
+ * Conventions for every call below:
+ *   - integers are fixed width; text and patterns are raw bytes (any of the
+ *     256 values, no terminator, case-sensitive);
+ *   - pattern id j is the index of the pattern in the array given to the
+ *     build call; identical patterns are accepted and each reports its own id;
+ *   - "device pointer" means memory on the GPU the handle was built on (for
+ *     example the data pointer of a torch CUDA tensor); "host pointer" means
+ *     ordinary process memory;
+ *   - calls returning int return GLOP_OK (0) or a negative glop error code;
+ *     calls returning a handle return NULL on error; in both cases
+ *     glop_last_error() / glop_last_error_message() describe the failure
+ *     (per calling thread).
+ */
+#ifndef GLOP_H
+#define GLOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define GLOP_OK 0
+#define GLOP_EINVAL (-1)   /* invalid argument (NULL pointer, empty pattern, bad option, small workspace) */
+#define GLOP_ENOMEM (-2)   /* host or device allocation failed, or the dictionary is too large */
+#define GLOP_EHIP (-3)     /* a HIP runtime call failed (message names it) */
+#define GLOP_ETOOLONG (-4) /* a pattern is longer than GLOP_MAX_PATTERN_LEN */
+#define GLOP_ENODEV (-5)   /* no usable GPU, or the handle has no device copy */
+
+#define GLOP_MAX_PATTERN_LEN 65535u
+#define GLOP_MAX_PATTERNS (1u << 24)
+
+/* One reported occurrence: 16 bytes, naturally aligned. */
+typedef struct {
+    uint64_t offset;     /* byte offset of the occurrence in the text of the call */
+    uint32_t pattern_id; /* index of the pattern in the build call's array */
+    uint32_t reserved;   /* always written as 0 */
+} glop_match_t;
+
+/* A compiled dictionary (the trie and its lookup tables); immutable once built. */
+typedef struct glop_dict *glop_handle_t;
+
+/*
+ * Build options (glop_build_ex).  Zero-initialise and set what you need; every
+ * setting changes only how the work is done, never the result.
+ *
+ *   filter      GLOP_FILTER_AUTO (0) = automatic (the q-gram filter whenever the
+ *                    dictionary is not empty);
+ *               GLOP_FILTER_NONE  = walk the trie from every offset, exactly as
+ *                    the one-walk-per-byte scheme of Section 5 does;
+ *               GLOP_FILTER_QGRAM = two stages: a bitmap summary of the
+ *                    patterns' leading q-byte strings rules out most offsets,
+ *                    and the trie walk runs from every offset not ruled out
+ *                    (the prefix filter + verify split of Sections 2 and 5,
+ *                    with the verify stage on the GPU and exact).
+ *   stride      0 = automatic; 1 = one filter probe per offset; 4 = one probe
+ *               per aligned 4-byte word (needs every pattern to be at least
+ *               qgram + 3 bytes long).
+ *   qgram       0 = automatic (min(4, shortest pattern)); else 1..4 and at most
+ *               the shortest pattern length.
+ *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
+ *               resident in LDS).
+ */
+#define GLOP_FILTER_AUTO 0
+#define GLOP_FILTER_NONE 1
+#define GLOP_FILTER_QGRAM 2
+typedef struct {
+    int32_t filter;
+    uint32_t stride;
+    uint32_t qgram;
+    uint32_t bitmap_log2;
+} glop_build_opts;
+
+/*
+ * Build a dictionary from n patterns (Section 4: the first phase builds the
+ * state machine from the patterns; Section 5: the failure transitions are
+ * dropped, leaving a trie of goto edges).
+ *
+ *   patterns  host array of n host pointers; pattern j is
+ *             patterns[j][0 .. lengths[j]).  May be NULL when n == 0.
+ *   lengths   host array of n lengths, each 1..GLOP_MAX_PATTERN_LEN.
+ *   n         0..GLOP_MAX_PATTERNS; n == 0 is a valid empty dictionary.
+ *
+ * The patterns are copied; the caller may free its arrays on return.  The
+ * compiled tables are uploaded to the current HIP device, to which the handle
+ * is bound.  Errors: GLOP_EINVAL (NULL array, zero length), GLOP_ETOOLONG,
+ * GLOP_ENOMEM, GLOP_EHIP / GLOP_ENODEV (upload failed or no GPU).
+ */
+glop_handle_t glop_build(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n);
+
+/* As glop_build, with options (opts may be NULL = all automatic). */
+glop_handle_t glop_build_ex(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
+                            const glop_build_opts *opts);
+
+/*
+ * Host-only compile: the same trie and tables as glop_build_ex, without any
+ * device upload (usable on machines with no GPU).  Such a handle serves the
+ * introspection calls and glop_cpu_walk; glop_match on it fails with
+ * GLOP_ENODEV.
+ */
+glop_handle_t glop_compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
+                           const glop_build_opts *opts);
+
+/* Release a handle and its device tables.  No match using it may still be in
+ * flight on any stream.  NULL is ignored. */
+void glop_free(glop_handle_t h);
+
+/*
+ * Match the dictionary against one text on the GPU (Section 5: one trie walk
+ * per byte offset; a mismatch ends the walk, a match carries it on into the
+ * following bytes).  Asynchronous on `stream`.
+ *
+ *   h            handle from glop_build / glop_build_ex, bound to the current device.
+ *   d_text       device pointer to len bytes (any alignment); may be NULL iff len == 0.
+ *   len          text length in bytes (0 allowed).
+ *   d_out        device array of max_matches records; receives the first
+ *                min(max_matches, |M|) records of M in (offset, id) order.
+ *                May be NULL iff max_matches == 0.
+ *   max_matches  capacity of d_out in records.  Truncation is not an error:
+ *                the counts are always complete, and the caller detects it
+ *                after the stream completes as sum(counts) > max_matches.
+ *   d_counts     device array of n uint64 counts, overwritten with C.  May be
+ *                NULL iff n == 0.
+ *   stream       a hipStream_t (NULL = the default stream).
+ *
+ * Device scratch is taken from the stream-ordered allocator of `stream` and
+ * released on it.  Returns once the work is enqueued.  The caller keeps every
+ * buffer alive until the stream has completed it.  Concurrent calls on one
+ * handle from different streams are safe (the handle is read-only).
+ * Errors: GLOP_EINVAL, GLOP_ENODEV (host-only handle or another device is
+ * current), GLOP_ENOMEM, GLOP_EHIP.
+ */
+int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
+               uint64_t max_matches, uint64_t *d_counts, void *stream);
+
+/* Bytes of device workspace glop_match_ws needs for a text of len bytes. */
+uint64_t glop_workspace_bytes(glop_handle_t h, uint64_t len);
+
+/*
+ * Optional timing hooks for benchmarks: non-NULL members are hipEvent_t
+ * handles that glop_match_ws records on the stream around its kernels.
+ */
+typedef struct {
+    void *scan_begin; /* before the scan kernel (the text-streaming kernel) */
+    void *scan_end;   /* after the scan kernel, before the emit kernel */
+    void *emit_end;   /* after the emit kernel */
+} glop_events_t;
+
+/*
+ * glop_match with caller-provided device workspace and an optional total.
+ *
+ *   d_total      device pointer to one uint64 receiving |M| (may be NULL).
+ *   d_workspace  device pointer, 256-byte aligned, at least
+ *                glop_workspace_bytes(h, len) bytes; owned by the caller, who
+ *                must not use it for anything else until the stream has
+ *                completed the call.  Two calls in flight at once need two
+ *                workspaces.
+ *   events       optional timing hooks (NULL = none).
+ * Allocates nothing.  Other arguments and errors as glop_match; a workspace
+ * that is NULL, misaligned or too small gives GLOP_EINVAL.
+ */
+int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
+                  uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                  uint64_t workspace_bytes, void *stream, const glop_events_t *events);
+
+/*
+ * The failureless-trie walk on the host CPU over the same compiled trie (the
+ * CPU counterpart the paper measures in Section 7).  A timing baseline and a
+ * check of the trie compiler; glop_match never calls it.
+ *
+ *   text         host pointer to len bytes.
+ *   out          host array of max_matches records (NULL iff max_matches == 0).
+ *   counts       host array of n counts (NULL iff n == 0), overwritten.
+ *   total        receives |M| (may be NULL).
+ *   threads      worker threads (<= 0 means 1); the result does not depend on it.
+ * Errors: GLOP_EINVAL, GLOP_ENOMEM.
+ */
+int glop_cpu_walk(glop_handle_t h, const uint8_t *text, uint64_t len, glop_match_t *out,
+                  uint64_t max_matches, uint64_t *counts, uint64_t *total, int threads);
+
+/* Introspection of a compiled dictionary. */
+typedef struct {
+    uint32_t num_patterns;
+    uint32_t min_len, max_len;
+    uint32_t num_classes;    /* byte classes incl. class 0 ("no pattern uses this byte") */
+    uint64_t num_states;     /* trie states incl. the root */
+    uint64_t table_bytes;    /* transition table size on the device */
+    uint64_t outlist_ids;    /* total entries of the per-state output lists */
+    int32_t filter;          /* GLOP_FILTER_NONE or GLOP_FILTER_QGRAM as chosen */
+    uint32_t stride, qgram, bitmap_log2;
+    uint64_t filter_keys;    /* distinct q-grams set in the bitmap */
+    uint64_t device_bytes;   /* device memory held by the handle */
+    int32_t device;          /* HIP device id, or -1 for a host-only handle */
+} glop_info_t;
+int glop_get_info(glop_handle_t h, glop_info_t *out);
+
+int glop_last_error(void);
+const char *glop_last_error_message(void);
+const char *glop_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLOP_H */

@@ -1,0 +1,230 @@
+"""Exact multi-pattern log matching on MI355X (failureless-trie walk, arXiv 1704.02278).
+
+A thin ctypes binding over ``libglop.so`` (the C-ABI in ``include/glop.h``).
+It only marshals arguments: tensors become device pointers, lists of bytes
+become pointer arrays; every step of the matching runs in the library's HIP
+kernels.  There is no fallback: if the library is missing, importing this
+package raises ImportError.
+
+Functions with the C names (``glop_build``, ``glop_match`` ...) mirror the
+C-ABI one to one; ``Dict`` is a convenience wrapper for torch tensors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+# torch first: it loads its HIP runtime (soname libamdhip64.so.7), which
+# libglop.so then binds to, so streams and events are shared with torch.
+import torch  # noqa: F401
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libglop.so"
+
+if not LIB_PATH.exists():
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1704_02278_amd.build`")
+
+GLOP_OK = 0
+GLOP_EINVAL = -1
+GLOP_ENOMEM = -2
+GLOP_EHIP = -3
+GLOP_ETOOLONG = -4
+GLOP_ENODEV = -5
+GLOP_FILTER_AUTO = 0
+GLOP_FILTER_NONE = 1
+GLOP_FILTER_QGRAM = 2
+GLOP_MAX_PATTERN_LEN = 65535
+MATCH_RECORD_BYTES = 16
+
+
+class glop_match_t(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint64), ("pattern_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class glop_build_opts(ctypes.Structure):
+    _fields_ = [("filter", ctypes.c_int32), ("stride", ctypes.c_uint32), ("qgram", ctypes.c_uint32),
+                ("bitmap_log2", ctypes.c_uint32)]
+
+
+class glop_events_t(ctypes.Structure):
+    _fields_ = [("scan_begin", ctypes.c_void_p), ("scan_end", ctypes.c_void_p), ("emit_end", ctypes.c_void_p)]
+
+
+class glop_info_t(ctypes.Structure):
+    _fields_ = [
+        ("num_patterns", ctypes.c_uint32), ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
+        ("num_classes", ctypes.c_uint32), ("num_states", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+        ("outlist_ids", ctypes.c_uint64), ("filter", ctypes.c_int32), ("stride", ctypes.c_uint32),
+        ("qgram", ctypes.c_uint32), ("bitmap_log2", ctypes.c_uint32), ("filter_keys", ctypes.c_uint64),
+        ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
+    ]
+
+
+_u8pp = ctypes.POINTER(ctypes.c_void_p)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+
+_lib = ctypes.CDLL(str(LIB_PATH))
+_SIGNATURES = {
+    "glop_build": (_vp, [_u8pp, _u32p, ctypes.c_uint32]),
+    "glop_build_ex": (_vp, [_u8pp, _u32p, ctypes.c_uint32, ctypes.POINTER(glop_build_opts)]),
+    "glop_compile": (_vp, [_u8pp, _u32p, ctypes.c_uint32, ctypes.POINTER(glop_build_opts)]),
+    "glop_free": (None, [_vp]),
+    "glop_match": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp]),
+    "glop_workspace_bytes": (_u64, [_vp, _u64]),
+    "glop_match_ws": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _vp,
+                                     ctypes.POINTER(glop_events_t)]),
+    "glop_cpu_walk": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_int]),
+    "glop_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(glop_info_t)]),
+    "glop_last_error": (ctypes.c_int, []),
+    "glop_last_error_message": (ctypes.c_char_p, []),
+    "glop_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+for _name, (_res, _args) in _SIGNATURES.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+EXPORTED = tuple(_SIGNATURES)
+
+
+class GlopError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = (glop_last_error_message() or b"").decode(errors="replace")
+        super().__init__(f"{what}: {glop_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc: int, what: str):
+    if rc != GLOP_OK:
+        raise GlopError(rc, what)
+
+
+def _pattern_arrays(patterns):
+    pats = [bytes(p) for p in patterns]
+    keep = [ctypes.create_string_buffer(p, len(p)) for p in pats]
+    ptrs = (ctypes.c_void_p * max(1, len(pats)))(*[ctypes.addressof(b) for b in keep])
+    lens = (ctypes.c_uint32 * max(1, len(pats)))(*[len(p) for p in pats])
+    return keep, ptrs, lens, len(pats)
+
+
+def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0):
+    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2))
+
+
+class Dict:
+    """A compiled dictionary on the current device (or host-only with ``device=False``)."""
+
+    def __init__(self, patterns, *, device: bool = True, filter=GLOP_FILTER_AUTO, stride=0, qgram=0,
+                 bitmap_log2=0):
+        keep, ptrs, lens, n = _pattern_arrays(patterns)
+        opts = _opts(filter, stride, qgram, bitmap_log2)
+        fn = glop_build_ex if device else glop_compile
+        h = fn(ctypes.cast(ptrs, _u8pp), lens, n, ctypes.byref(opts))
+        if not h:
+            raise GlopError(glop_last_error(), "glop_build_ex" if device else "glop_compile")
+        self._h = ctypes.c_void_p(h)
+        self.num_patterns = n
+        self.pattern_lengths = [len(p) for p in patterns]
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        out = glop_info_t()
+        _check(glop_get_info(self._h, ctypes.byref(out)), "glop_get_info")
+        return {name: getattr(out, name) for name, _ in glop_info_t._fields_}
+
+    def workspace_bytes(self, length: int) -> int:
+        return int(glop_workspace_bytes(self._h, int(length)))
+
+    def match_into(self, text, out, counts, *, max_matches=None, total=None, workspace=None, stream=None,
+                   events=None, length=None):
+        """Enqueue a match into caller-owned tensors (no allocation, no sync).
+
+        text: uint8 CUDA tensor; out: int64 CUDA tensor [cap, 2] (16-byte
+        records); counts: int64 CUDA tensor [n]; total: int64 CUDA tensor [1]
+        or None; workspace: uint8 CUDA tensor of >= workspace_bytes(len)
+        bytes (None = let the library allocate on the stream).
+        """
+        import torch
+
+        n = int(text.numel()) if length is None else int(length)
+        cap = int(out.shape[0]) if max_matches is None else int(max_matches)
+        s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+        if workspace is None:
+            _check(glop_match(self._h, text.data_ptr(), n, out.data_ptr(), cap, counts.data_ptr(), s),
+                   "glop_match")
+            return
+        ev = None
+        if events is not None:
+            ev = ctypes.byref(glop_events_t(*events))
+        _check(glop_match_ws(self._h, text.data_ptr(), n, out.data_ptr(), cap, counts.data_ptr(),
+                             total.data_ptr() if total is not None else None, workspace.data_ptr(),
+                             int(workspace.numel()), s, ev), "glop_match_ws")
+
+    def match(self, text, max_matches=None, stream=None):
+        """Match a uint8 CUDA tensor; returns (offsets i64[M], ids i64[M], counts i64[n], total).
+
+        With ``max_matches=None`` the output is sized to fit every match (a
+        second pass runs if the first guess was short; this synchronises).
+        ``offsets`` and ``ids`` are views of the 16-byte records (the id column
+        holds pattern_id with the zero ``reserved`` word above it).
+        """
+        import torch
+
+        dev = text.device
+        n = int(text.numel())
+        counts = torch.empty(max(1, self.num_patterns), dtype=torch.int64, device=dev)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(self.workspace_bytes(n) + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:]
+        cap = max(1024, n // 1024) if max_matches is None else int(max_matches)
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+        self.match_into(text, out, counts, max_matches=cap, total=total, workspace=ws, stream=stream)
+        got = int(total.item())
+        if max_matches is None and got > cap:
+            cap = got
+            out = torch.empty((cap, 2), dtype=torch.int64, device=dev)
+            self.match_into(text, out, counts, max_matches=cap, total=total, workspace=ws, stream=stream)
+            got = int(total.item())
+        k = min(cap, got)
+        return out[:k, 0], out[:k, 1], counts[: self.num_patterns], got
+
+    def cpu_walk(self, text, threads: int = 1, max_matches=None):
+        """Failureless-trie walk on the host (baseline); returns numpy arrays like ``match``."""
+        import numpy as np
+
+        t = np.frombuffer(bytes(text), dtype=np.uint8) if not isinstance(text, np.ndarray) else text
+        t = np.ascontiguousarray(t)
+        counts = np.zeros(max(1, self.num_patterns), dtype=np.uint64)
+        total = ctypes.c_uint64(0)
+        if max_matches is None:
+            _check(glop_cpu_walk(self._h, t.ctypes.data, t.size, None, 0, counts.ctypes.data,
+                                 ctypes.byref(total), threads), "glop_cpu_walk")
+            max_matches = total.value
+        rec = np.zeros((max(1, max_matches), 2), dtype=np.uint64)
+        _check(glop_cpu_walk(self._h, t.ctypes.data, t.size, rec.ctypes.data, max_matches, counts.ctypes.data,
+                             ctypes.byref(total), threads), "glop_cpu_walk")
+        k = min(max_matches, total.value)
+        return rec[:k, 0], rec[:k, 1] & np.uint64(0xFFFFFFFF), counts[: self.num_patterns], int(total.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            glop_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(patterns, **opts) -> Dict:
+    return Dict(patterns, **opts)

@@ -1,0 +1,573 @@
+// Matching kernels for gfx950 (CDNA4, wave64).
+//
+// Every byte offset of the text starts a walk of the failureless trie
+// (Section 5).  The work is split in two kernels:
+//
+// scan  -- streams the text once from HBM.  Each wave owns 8 KiB tiles; a lane
+//          holds 16 consecutive bytes per 1 KiB round (one coalesced 16-byte
+//          load).  With the q-gram filter, the lane first probes an LDS bitmap
+//          that summarises the trie's first q levels: an offset whose q-gram
+//          (or, at stride 4, whose covering aligned 4-byte word) misses the
+//          bitmap cannot start any pattern and needs no walk.  This is the
+//          prefix-filter stage of Sections 2 and 5, made exact because every
+//          surviving offset is then walked through the full trie.  Surviving
+//          offsets are appended in order to a per-wave LDS ring and walked
+//          64 at a time, one per lane, so walks run with full waves instead of
+//          the few divergent lanes Section 5 describes.  A walk reads bytes
+//          past its tile as needed (the overlap of at least the longest
+//          pattern minus one byte that Section 4 requires between chunks).
+//          Each tile's matched starts (offset, deepest terminal state) are
+//          staged in workspace; the tile's record count is written out.
+// emit  -- turns the per-tile record counts into output positions (sum over
+//          earlier workgroups, then a block scan over the tiles) and writes the
+//          (offset, id) records in order, plus the per-pattern counts.  A tile
+//          with more matched starts than the staging slots is rescanned here
+//          and written directly.
+//
+// No workgroup ever waits for another, so the kernels are safe to run beside
+// any other work on the device.
+#include <hip/hip_runtime.h>
+
+#include "glop_kernels.hpp"
+
+namespace glop {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWaves = 16;                        // waves per workgroup
+constexpr int kBlock = kWave * kWaves;            // 1024 threads
+constexpr int kRoundBytes = kWave * 16;           // 1 KiB: 16 bytes per lane
+constexpr int kRounds = 8;                        // rounds per tile
+constexpr int kTileBytes = kRoundBytes * kRounds; // 8 KiB per wave tile
+constexpr int kQueueCap = 2048;                   // per-wave ring of candidate offsets (u16)
+constexpr uint32_t kStageCap = 16;                // staged matched starts per tile
+constexpr uint32_t kQueueBytes = kWaves * kQueueCap * 2;
+
+struct ScanParams {
+    GlopDevDict d;
+    const uint8_t *text;   // caller's text
+    const uint8_t *abase;  // text rounded down to 16 bytes; coordinates x are relative to it
+    uint64_t len;
+    uint64_t head;         // text - abase (0..15)
+    uint64_t span_end;     // head + len
+    uint64_t valid_end;    // x < valid_end (and x >= head) can start a pattern
+    uint64_t ntiles;
+    uint64_t tiles_per_wg;
+    uint32_t bm_bytes;     // bitmap bytes staged in LDS (0 without filter)
+    uint64_t *tile_rec;    // records per tile
+    uint32_t *tile_nm;     // matched starts per tile
+    uint64_t *staging;     // kStageCap per tile: (offset in tile << 32) | state
+    uint64_t *wgsum;       // records per scan workgroup
+    uint64_t *counts;      // per-pattern counts (zeroed by the scan kernel)
+};
+
+struct EmitParams {
+    glop_match_t *out;
+    uint64_t max_matches;
+    uint64_t *total;
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    return (1ull << lane) - 1ull;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Inclusive scan over the wave; returns the exclusive prefix, `total` = sum.
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    total = __shfl(incl, kWave - 1);
+    return incl - v;
+}
+
+// 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
+__device__ __forceinline__ uint4 load16(const ScanParams &P, uint64_t x) {
+    if (x >= P.head && x + 16 <= P.span_end) return *reinterpret_cast<const uint4 *>(P.abase + x);
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        uint64_t y = x + k;
+        uint32_t b = (y >= P.head && y < P.span_end) ? (uint32_t)P.abase[y] : 0u;
+        uint32_t sh = 8 * (k & 3);
+        if (k < 4) w0 |= b << sh;
+        else if (k < 8) w1 |= b << sh;
+        else if (k < 12) w2 |= b << sh;
+        else w3 |= b << sh;
+    }
+    return make_uint4(w0, w1, w2, w3);
+}
+
+// 4 text bytes at aligned coordinate x (multiple of 4); outside reads as 0.
+__device__ __forceinline__ uint32_t load4(const ScanParams &P, uint64_t x) {
+    if (x >= P.head && x + 4 <= P.span_end) return *reinterpret_cast<const uint32_t *>(P.abase + x);
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint64_t y = x + k;
+        w |= ((y >= P.head && y < P.span_end) ? (uint32_t)P.abase[y] : 0u) << (8 * k);
+    }
+    return w;
+}
+
+__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t lg) {
+    uint32_t slot = glop_qgram_slot(g & qmask, lg);
+    return (bm[slot >> 5] >> (slot & 31)) & 1u;
+}
+
+// Offsets x .. x+15 that may start a pattern: head <= x+u < valid_end.
+__device__ __forceinline__ uint32_t valid_mask16(const ScanParams &P, uint64_t x) {
+    int64_t lo = (int64_t)P.head - (int64_t)x;
+    int64_t hi = (int64_t)P.valid_end - (int64_t)x;
+    lo = lo < 0 ? 0 : (lo > 16 ? 16 : lo);
+    hi = hi < 0 ? 0 : (hi > 16 ? 16 : hi);
+    if (hi <= lo) return 0u;
+    return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// The failureless walk from text offset i (Section 5): follow goto edges while
+// they exist; return the deepest terminal state passed (0 = none).
+__device__ __forceinline__ uint32_t walk(const ScanParams &P, const uint8_t *cls, uint64_t i) {
+    const uint32_t C = P.d.num_classes;
+    const uint32_t *delta = P.d.delta;
+    uint32_t s = 0, last = 0;
+    for (uint64_t p = i; p < P.len; ++p) {
+        uint32_t c = cls[P.text[p]];
+        uint32_t e = delta[(uint64_t)s * C + c];
+        if (e == 0) break;
+        s = e & GLOP_STATE_MASK;
+        if (e & GLOP_TERM_BIT) last = s;
+    }
+    return last;
+}
+
+// Sink of the scan kernel: stage matched starts of the tile, count records.
+struct StageSink {
+    uint32_t nm = 0;   // matched starts so far (wave-uniform)
+    uint64_t rec = 0;  // records so far (wave-uniform)
+
+    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, uint64_t /*x0*/, uint32_t off,
+                                          uint32_t last) {
+        const bool m = last != 0;
+        const uint64_t bal = __ballot(m);
+        if (bal == 0) return;
+        const uint32_t pos = nm + (uint32_t)__popcll(bal & lanemask_lt());
+        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = ((uint64_t)off << 32) | last;
+        nm += (uint32_t)__popcll(bal);
+        rec += wave_sum_u32(m ? P.d.term[2 * last + 1] : 0u);
+    }
+    __device__ __forceinline__ void finish(const ScanParams &P, uint64_t t) {
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            P.tile_rec[t] = rec;
+            P.tile_nm[t] = nm;
+        }
+    }
+};
+
+// Sink of the emit kernel's rescan: write the records directly, in order.
+struct DirectSink {
+    const EmitParams *E;
+    uint64_t base;        // output position of the tile's first record
+    uint64_t cursor = 0;  // records written so far in the tile
+
+    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t /*t*/, uint64_t x0, uint32_t off,
+                                          uint32_t last) {
+        const bool m = last != 0;
+        if (__ballot(m) == 0) return;
+        const uint32_t first = m ? P.d.term[2 * last] : 0u;
+        const uint32_t cnt = m ? P.d.term[2 * last + 1] : 0u;
+        uint32_t tot;
+        const uint32_t excl = wave_excl_scan_u32(cnt, tot);
+        if (m) {
+            const uint64_t i = x0 + off - P.head;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t id = P.d.outids[first + k];
+                const uint64_t pos = base + cursor + excl + k;
+                if (pos < E->max_matches) E->out[pos] = glop_match_t{i, id, 0u};
+                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+            }
+        }
+        cursor += tot;
+    }
+    __device__ __forceinline__ void finish(const ScanParams &, uint64_t) {}
+};
+
+// One wave processes tile t: load, filter, queue, walk.  Returns the tile's
+// record count as seen by the sink (wave-uniform).
+template <int STRIDE, bool FILTER, class Sink>
+__device__ __forceinline__ void scan_tile(const ScanParams &P, uint64_t t, const uint32_t *bm,
+                                          const uint8_t *cls, uint16_t *queue, Sink &sink) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t x0 = t * (uint64_t)kTileBytes;
+    const uint32_t qmask = P.d.qmask, lg = P.d.bitmap_log2;
+
+    uint4 v[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) v[r] = load16(P, x0 + (uint64_t)r * kRoundBytes + lane * 16u);
+    const uint32_t extra = FILTER ? load4(P, x0 + kTileBytes) : 0u;
+
+    // Stride 4: probe bit of each aligned word, 4 per round, packed.
+    uint32_t pbits = 0, extra_bit = 0;
+    if (FILTER && STRIDE == 4) {
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            pbits |= probe(bm, v[r].x, qmask, lg) << (4 * r);
+            pbits |= probe(bm, v[r].y, qmask, lg) << (4 * r + 1);
+            pbits |= probe(bm, v[r].z, qmask, lg) << (4 * r + 2);
+            pbits |= probe(bm, v[r].w, qmask, lg) << (4 * r + 3);
+        }
+        extra_bit = probe(bm, extra, qmask, lg);
+    }
+    const uint32_t pbits_lane0 = __builtin_amdgcn_readfirstlane(pbits);
+
+    uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const uint64_t xl = x0 + (uint64_t)r * kRoundBytes + lane * 16u;
+        uint32_t mask;
+        if (!FILTER) {
+            mask = 0xFFFFu;
+        } else if (STRIDE == 4) {
+            // Offset x maps to the aligned word at roundup4(x): offsets 1..4 of
+            // the lane to word 1, ..., 13..15 to the next lane's word 0.
+            const uint64_t b0 = __ballot((pbits >> (4 * r)) & 1u);
+            uint32_t nb0;
+            if (lane < kWave - 1) nb0 = (uint32_t)(b0 >> (lane + 1)) & 1u;
+            else nb0 = (r + 1 < kRounds) ? ((pbits_lane0 >> (4 * (r + 1))) & 1u) : extra_bit;
+            const uint32_t pb = (pbits >> (4 * r)) & 0xFu;
+            mask = (pb & 1u) | (((pb >> 1) & 1u) * 0x001Eu) | (((pb >> 2) & 1u) * 0x01E0u) |
+                   (((pb >> 3) & 1u) * 0x1E00u) | (nb0 * 0xE000u);
+        } else {
+            // Stride 1: the q-gram at each of the lane's 16 offsets.
+            // Bytes 16..19 of the lane = the next lane's first word; for the
+            // last lane, the next round's lane 0 (read wave-wide, before any
+            // divergence) or the word after the tile.
+            const uint32_t next0 =
+                (r + 1 < kRounds) ? __builtin_amdgcn_readfirstlane(v[(r + 1) % kRounds].x) : extra;
+            uint32_t nx = __shfl_down(v[r].x, 1);
+            if (lane == kWave - 1) nx = next0;
+            const uint32_t w[5] = {v[r].x, v[r].y, v[r].z, v[r].w, nx};
+            mask = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
+                                           : w[u >> 2];
+                mask |= probe(bm, g, qmask, lg) << u;
+            }
+        }
+        mask &= valid_mask16(P, xl);
+
+        // Ordered append of this round's candidates to the ring.
+        if (__ballot(mask != 0) != 0) {
+            const uint32_t c = (uint32_t)__popc(mask);
+            uint32_t pre = 0, tot = 0;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                const uint64_t bal = __ballot((c >> b) & 1u);
+                pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
+                tot += (uint32_t)__popcll(bal) << b;
+            }
+            uint32_t pos = qtail + pre;
+            uint32_t mm = mask;
+            const uint32_t base_off = (uint32_t)r * kRoundBytes + lane * 16u;
+            while (mm) {
+                const uint32_t u = (uint32_t)__builtin_ctz(mm);
+                mm &= mm - 1u;
+                queue[(pos++) & (kQueueCap - 1)] = (uint16_t)(base_off + u);
+            }
+            qtail += tot;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // Walk full batches: one candidate per lane.
+        while (qtail - qhead >= (uint32_t)kWave) {
+            const uint32_t off = queue[(qhead + lane) & (kQueueCap - 1)];
+            const uint32_t last = walk(P, cls, x0 + off - P.head);
+            sink.batch(P, t, x0, off, last);
+            qhead += kWave;
+        }
+    }
+    // Last partial batch.
+    if (qtail != qhead) {
+        const uint32_t k = qtail - qhead;
+        const bool act = lane < k;
+        const uint32_t off = act ? queue[(qhead + lane) & (kQueueCap - 1)] : 0u;
+        const uint32_t last = act ? walk(P, cls, x0 + off - P.head) : 0u;
+        sink.batch(P, t, x0, off, last);
+    }
+    sink.finish(P, t);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Copy the bitmap and byte classes into LDS.
+template <bool FILTER>
+__device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, uint8_t *cls) {
+    if (FILTER) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.bitmap);
+        uint4 *dst = reinterpret_cast<uint4 *>(bm);
+        for (uint32_t k = threadIdx.x; k < P.bm_bytes / 16; k += kBlock) dst[k] = src[k];
+    }
+    if (threadIdx.x < 64)
+        reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
+}
+
+template <int STRIDE, bool FILTER>
+__global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint64_t wsum[kWaves];
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
+    uint8_t *cls = lds + P.bm_bytes;
+    uint16_t *queues = reinterpret_cast<uint16_t *>(cls + 256);
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+
+    // Counts are accumulated by the emit kernel, which runs after this one.
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < P.d.num_patterns;
+         k += (uint64_t)gridDim.x * kBlock)
+        P.counts[k] = 0;
+    stage_tables<FILTER>(P, bm, cls);
+    __syncthreads();
+
+    const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
+    const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
+    uint64_t total = 0;
+    for (uint64_t t = tb + wave; t < te; t += kWaves) {
+        StageSink sink;
+        scan_tile<STRIDE, FILTER>(P, t, bm, cls, queues + wave * kQueueCap, sink);
+        total += sink.rec;
+    }
+    if (lane == 0) wsum[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int w = 0; w < kWaves; ++w) s += wsum[w];
+        P.wgsum[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan over the block (1024 threads); `total` = block sum.
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh, uint64_t &total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint64_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) sh[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const uint64_t w = lane < kWaves ? sh[lane] : 0ull;
+        uint64_t wi = w;
+#pragma unroll
+        for (int o = 1; o < kWaves; o <<= 1) {
+            uint64_t y = __shfl_up(wi, o);
+            if (lane >= o) wi += y;
+        }
+        if (lane < kWaves) sh[lane] = wi - w;
+        if (lane == kWaves - 1) sh[kWaves] = wi;
+    }
+    __syncthreads();
+    const uint64_t excl = sh[wave] + incl - v;
+    total = sh[kWaves];
+    __syncthreads();
+    return excl;
+}
+
+template <int STRIDE, bool FILTER>
+__global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitParams E) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint64_t scan_sh[kWaves + 1];
+    __shared__ uint64_t red[kWaves];
+    __shared__ uint32_t n_over, any_over;
+    __shared__ uint64_t over_tile[kBlock];
+    __shared__ uint64_t over_base[kBlock];
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
+    uint8_t *cls = lds + P.bm_bytes;
+    uint16_t *queues = reinterpret_cast<uint16_t *>(cls + 256);
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+
+    const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
+    const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
+
+    // Records of all earlier workgroups, and whether any tile here overflowed.
+    uint64_t part = 0;
+    for (uint32_t g = threadIdx.x; g < blockIdx.x; g += kBlock) part += P.wgsum[g];
+    uint32_t over = 0;
+    for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (threadIdx.x == 0) any_over = 0;
+    __syncthreads();
+    if (lane == 0) red[wave] = part;
+    if (over) atomicOr(&any_over, 1u);
+    __syncthreads();
+    uint64_t base = 0;
+    for (int w = 0; w < kWaves; ++w) base += red[w];
+    if (any_over) {
+        stage_tables<FILTER>(P, bm, cls);
+        __syncthreads();
+    }
+
+    for (uint64_t c0 = tb; c0 < te; c0 += kBlock) {
+        const uint64_t t = c0 + threadIdx.x;
+        const bool in = t < te;
+        const uint64_t rec = in ? P.tile_rec[t] : 0ull;
+        uint64_t chunk_total;
+        const uint64_t tile_base = base + block_excl_scan_u64(rec, scan_sh, chunk_total);
+        if (threadIdx.x == 0) n_over = 0;
+        __syncthreads();
+        if (rec > 0) {
+            const uint32_t nm = P.tile_nm[t];
+            if (nm <= kStageCap) {
+                uint64_t pos = tile_base;
+                for (uint32_t e = 0; e < nm; ++e) {
+                    const uint64_t ent = P.staging[t * kStageCap + e];
+                    const uint32_t st = (uint32_t)ent;
+                    const uint64_t i = t * (uint64_t)kTileBytes + (ent >> 32) - P.head;
+                    const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
+                    for (uint32_t k = 0; k < cnt; ++k, ++pos) {
+                        const uint32_t id = P.d.outids[first + k];
+                        if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, 0u};
+                        atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                    }
+                }
+            } else {
+                const uint32_t slot = atomicAdd(&n_over, 1u);
+                over_tile[slot] = t;
+                over_base[slot] = tile_base;
+            }
+        }
+        __syncthreads();
+        for (uint32_t o = wave; o < n_over; o += kWaves) {
+            DirectSink sink{&E, over_base[o]};
+            scan_tile<STRIDE, FILTER>(P, over_tile[o], bm, cls, queues + wave * kQueueCap, sink);
+        }
+        __syncthreads();
+        base += chunk_total;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0 && E.total) *E.total = base;
+}
+
+__global__ void glop_zero_kernel(uint64_t *counts, uint32_t n, uint64_t *total) {
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) counts[k] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0;
+}
+
+struct Geometry {
+    uint64_t ntiles, tiles_per_wg;
+    uint32_t grid;
+    uint64_t off_rec, off_nm, off_stage, off_wgsum, bytes;
+};
+
+constexpr uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+Geometry geometry(uint64_t len, int num_cus) {
+    Geometry g{};
+    // Tiles cover the text plus up to 15 leading bytes of alignment.
+    g.ntiles = (len + 15 + kTileBytes - 1) / kTileBytes;
+    const uint64_t wgs = (uint64_t)(num_cus > 0 ? num_cus : 1);
+    g.tiles_per_wg = g.ntiles ? (g.ntiles + wgs - 1) / wgs : 1;
+    g.grid = (uint32_t)(g.ntiles ? (g.ntiles + g.tiles_per_wg - 1) / g.tiles_per_wg : 0);
+    g.off_rec = 0;
+    g.off_nm = align256(g.off_rec + g.ntiles * 8);
+    g.off_stage = align256(g.off_nm + g.ntiles * 4);
+    g.off_wgsum = align256(g.off_stage + g.ntiles * kStageCap * 8);
+    g.bytes = align256(g.off_wgsum + (uint64_t)g.grid * 8);
+    if (g.bytes == 0) g.bytes = 256;
+    return g;
+}
+
+template <int STRIDE, bool FILTER>
+hipError_t launch_pair(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t stream,
+                       const glop_events_t *ev) {
+    const size_t lds = (size_t)P.bm_bytes + 256 + kQueueBytes;
+    if (ev && ev->scan_begin) {
+        hipError_t e = hipEventRecord((hipEvent_t)ev->scan_begin, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER>), dim3(grid), dim3(kBlock), lds, stream, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && ev->scan_end) {
+        e = hipEventRecord((hipEvent_t)ev->scan_end, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER>), dim3(grid), dim3(kBlock), lds, stream, P, E);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && ev->emit_end) e = hipEventRecord((hipEvent_t)ev->emit_end, stream);
+    return e;
+}
+
+template <int STRIDE, bool FILTER>
+hipError_t set_lds_limit(int bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace
+
+uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus).bytes; }
+
+hipError_t prepare_kernels() {
+    const int bytes = (1 << 19) / 8 + 256 + (int)kQueueBytes;
+    hipError_t e = set_lds_limit<1, false>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<1, true>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<4, true>(bytes);
+    return e;
+}
+
+hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
+    const GlopDevDict &d = a.d;
+    const bool trivial = d.num_patterns == 0 || a.len < d.min_len;
+    if (trivial) {
+        if (a.events && a.events->scan_begin) (void)hipEventRecord((hipEvent_t)a.events->scan_begin, stream);
+        const uint32_t n = d.num_patterns;
+        const uint32_t blocks = n ? (n + 255) / 256 : 1;
+        hipLaunchKernelGGL(glop_zero_kernel, dim3(blocks > 1024 ? 1024 : blocks), dim3(256), 0, stream,
+                           a.counts, n, a.total);
+        hipError_t e = hipGetLastError();
+        if (a.events && a.events->scan_end) (void)hipEventRecord((hipEvent_t)a.events->scan_end, stream);
+        if (a.events && a.events->emit_end) (void)hipEventRecord((hipEvent_t)a.events->emit_end, stream);
+        return e;
+    }
+    const Geometry g = geometry(a.len, a.num_cus);
+    ScanParams P{};
+    P.d = d;
+    P.text = a.text;
+    P.head = reinterpret_cast<uintptr_t>(a.text) & 15u;
+    P.abase = a.text - P.head;
+    P.len = a.len;
+    P.span_end = P.head + a.len;
+    P.valid_end = P.head + a.len - d.min_len + 1;
+    P.ntiles = g.ntiles;
+    P.tiles_per_wg = g.tiles_per_wg;
+    P.bm_bytes = d.filter == GLOP_FILTER_QGRAM ? (1u << d.bitmap_log2) / 8 : 0u;
+    uint8_t *ws = static_cast<uint8_t *>(a.workspace);
+    P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);
+    P.tile_nm = reinterpret_cast<uint32_t *>(ws + g.off_nm);
+    P.staging = reinterpret_cast<uint64_t *>(ws + g.off_stage);
+    P.wgsum = reinterpret_cast<uint64_t *>(ws + g.off_wgsum);
+    P.counts = a.counts;
+    EmitParams E{a.out, a.max_matches, a.total};
+    if (d.filter != GLOP_FILTER_QGRAM) return launch_pair<1, false>(P, E, g.grid, stream, a.events);
+    if (d.stride == 4) return launch_pair<4, true>(P, E, g.grid, stream, a.events);
+    return launch_pair<1, true>(P, E, g.grid, stream, a.events);
+}
+
+}  // namespace glop

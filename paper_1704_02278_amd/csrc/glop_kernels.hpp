@@ -1,0 +1,34 @@
+// Host-visible interface of the matching kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glop.h"
+#include "glop_layout.hpp"
+
+namespace glop {
+
+struct MatchLaunch {
+    GlopDevDict d;
+    const uint8_t *text;
+    uint64_t len;
+    glop_match_t *out;
+    uint64_t max_matches;
+    uint64_t *counts;
+    uint64_t *total;  // may be null
+    void *workspace;
+    uint64_t workspace_bytes;
+    int num_cus;
+    const glop_events_t *events;  // may be null
+};
+
+// Device workspace needed for a text of `len` bytes (any alignment).
+uint64_t workspace_bytes(uint64_t len, int num_cus);
+
+// Enqueue the whole match on `stream`.
+hipError_t launch_match(const MatchLaunch &a, hipStream_t stream);
+
+// One-time per-device kernel attribute setup (dynamic LDS above 64 KiB).
+hipError_t prepare_kernels();
+
+}  // namespace glop

@@ -1,0 +1,286 @@
+// Host-side compiler of the failureless trie (Section 4's first phase, with the
+// failure transitions of Section 5 removed) and the CPU walk over it.
+#include "glop_trie.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "glop_layout.hpp"
+
+namespace glop {
+
+namespace {
+
+constexpr uint64_t kMaxTableBytes = 16ull << 30;  // dense table ceiling on the device
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+uint32_t ceil_log2(uint64_t v) {
+    uint32_t k = 0;
+    while ((1ull << k) < v) ++k;
+    return k;
+}
+
+uint32_t load_qgram(const uint8_t *p, uint32_t q) {
+    uint32_t g = 0;
+    for (uint32_t k = 0; k < q; ++k) g |= (uint32_t)p[k] << (8 * k);
+    return g;
+}
+
+}  // namespace
+
+int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
+            const glop_build_opts *opts, Compiled &c, std::string &err) {
+    glop_build_opts o{};
+    if (opts) o = *opts;
+    if (n > GLOP_MAX_PATTERNS) {
+        err = "too many patterns";
+        return GLOP_EINVAL;
+    }
+    if (n > 0 && (!patterns || !lengths)) {
+        err = "NULL pattern or length array";
+        return GLOP_EINVAL;
+    }
+    c = Compiled{};
+    c.num_patterns = n;
+    c.min_len = n ? 0xFFFFFFFFu : 0;
+    bool used[256] = {};
+    for (uint32_t j = 0; j < n; ++j) {
+        if (lengths[j] == 0) {
+            err = "pattern " + std::to_string(j) + " is empty";
+            return GLOP_EINVAL;
+        }
+        if (lengths[j] > GLOP_MAX_PATTERN_LEN) {
+            err = "pattern " + std::to_string(j) + " is longer than GLOP_MAX_PATTERN_LEN";
+            return GLOP_ETOOLONG;
+        }
+        if (!patterns[j]) {
+            err = "pattern " + std::to_string(j) + " is NULL";
+            return GLOP_EINVAL;
+        }
+        c.min_len = std::min(c.min_len, lengths[j]);
+        c.max_len = std::max(c.max_len, lengths[j]);
+        for (uint32_t k = 0; k < lengths[j]; ++k) used[patterns[j][k]] = true;
+    }
+    if (o.filter != GLOP_FILTER_AUTO && o.filter != GLOP_FILTER_NONE && o.filter != GLOP_FILTER_QGRAM) {
+        err = "unknown filter option";
+        return GLOP_EINVAL;
+    }
+
+    // Byte classes: class 0 = no pattern uses the byte; the rest in byte order.
+    uint32_t C = 1;
+    for (int b = 0; b < 256; ++b)
+        if (used[b]) c.cls[b] = (uint8_t)C++;
+    c.num_classes = C;
+
+    try {
+        // Insert every pattern (goto edges only), first-come state numbering.
+        std::vector<uint32_t> rows(C, 0);
+        std::vector<uint32_t> end_state(n);
+        uint64_t S = 1;
+        for (uint32_t j = 0; j < n; ++j) {
+            uint64_t s = 0;
+            for (uint32_t k = 0; k < lengths[j]; ++k) {
+                uint64_t idx = s * C + c.cls[patterns[j][k]];
+                uint32_t nx = rows[idx];
+                if (nx == 0) {
+                    if ((S + 1) * C * 4 > kMaxTableBytes || S + 1 > GLOP_STATE_MASK) {
+                        err = "dictionary too large for the dense transition table";
+                        return GLOP_ENOMEM;
+                    }
+                    nx = (uint32_t)S++;
+                    rows.resize(S * C, 0);
+                    rows[idx] = nx;
+                }
+                s = nx;
+            }
+            end_state[j] = (uint32_t)s;
+        }
+        c.num_states = (uint32_t)S;
+
+        // Pattern ids ending at each (old) state, ascending: counting sort.
+        std::vector<uint32_t> ids_at(S + 1, 0), ids(n);
+        for (uint32_t j = 0; j < n; ++j) ids_at[end_state[j] + 1]++;
+        for (uint64_t s = 0; s < S; ++s) ids_at[s + 1] += ids_at[s];
+        {
+            std::vector<uint32_t> fill(ids_at.begin(), ids_at.end() - 1);
+            for (uint32_t j = 0; j < n; ++j) ids[fill[end_state[j]]++] = j;
+        }
+        auto is_term_old = [&](uint32_t s) { return ids_at[s + 1] > ids_at[s]; };
+
+        // Breadth-first renumbering (children visited in class order).
+        std::vector<uint32_t> order;
+        order.reserve(S);
+        std::vector<uint32_t> new_id(S, kNone);
+        order.push_back(0);
+        new_id[0] = 0;
+        for (size_t q = 0; q < order.size(); ++q) {
+            uint32_t s = order[q];
+            for (uint32_t k = 1; k < C; ++k) {
+                uint32_t ch = rows[(uint64_t)s * C + k];
+                if (ch) {
+                    new_id[ch] = (uint32_t)order.size();
+                    order.push_back(ch);
+                }
+            }
+        }
+
+        c.delta.assign(S * C, 0);
+        c.term.assign(2 * S, 0);
+        std::vector<uint32_t> anc(S, kNone);  // nearest terminal strict ancestor (new ids)
+        std::vector<uint32_t> merged;
+        for (uint64_t ns = 0; ns < S; ++ns) {
+            uint32_t old = order[ns];
+            bool term = is_term_old(old);
+            if (term) {
+                // Output list = the nearest terminal ancestor's list merged with
+                // the ids ending here; both are ascending.
+                merged.clear();
+                const uint32_t *own = ids.data() + ids_at[old];
+                size_t own_n = ids_at[old + 1] - ids_at[old];
+                if (anc[ns] != kNone) {
+                    size_t a_first = c.term[2 * anc[ns]], a_n = c.term[2 * anc[ns] + 1];
+                    merged.resize(a_n + own_n);
+                    std::merge(c.outids.begin() + a_first, c.outids.begin() + a_first + a_n, own, own + own_n,
+                               merged.begin());
+                } else {
+                    merged.assign(own, own + own_n);
+                }
+                if (c.outids.size() + merged.size() > 0xFFFFFFFFull) {
+                    err = "output lists too large";
+                    return GLOP_ENOMEM;
+                }
+                c.term[2 * ns] = (uint32_t)c.outids.size();
+                c.term[2 * ns + 1] = (uint32_t)merged.size();
+                c.outids.insert(c.outids.end(), merged.begin(), merged.end());
+            }
+            for (uint32_t k = 1; k < C; ++k) {
+                uint32_t ch = rows[(uint64_t)old * C + k];
+                if (!ch) continue;
+                uint32_t nch = new_id[ch];
+                c.delta[ns * C + k] = nch | (is_term_old(ch) ? GLOP_TERM_BIT : 0u);
+                anc[nch] = term ? (uint32_t)ns : anc[ns];
+            }
+        }
+
+        // Filter (q-gram bitmap) parameters and keys.
+        int32_t filter = o.filter == GLOP_FILTER_AUTO ? (n ? GLOP_FILTER_QGRAM : GLOP_FILTER_NONE) : o.filter;
+        if (n == 0) filter = GLOP_FILTER_NONE;
+        c.filter = filter;
+        if (filter == GLOP_FILTER_QGRAM) {
+            uint32_t q = o.qgram ? o.qgram : std::min<uint32_t>(4, c.min_len);
+            if (q < 1 || q > 4 || q > c.min_len) {
+                err = "qgram must be 1..4 and at most the shortest pattern length";
+                return GLOP_EINVAL;
+            }
+            uint32_t stride = o.stride ? o.stride : (c.min_len >= q + 3 ? 4u : 1u);
+            if (stride != 1 && stride != 4) {
+                err = "stride must be 1 or 4";
+                return GLOP_EINVAL;
+            }
+            if (stride == 4 && c.min_len < q + 3) {
+                err = "stride 4 needs every pattern to be at least qgram + 3 bytes";
+                return GLOP_EINVAL;
+            }
+            std::vector<uint32_t> keys;
+            keys.reserve((size_t)n * stride);
+            for (uint32_t j = 0; j < n; ++j)
+                for (uint32_t t = 0; t < stride; ++t) keys.push_back(load_qgram(patterns[j] + t, q));
+            std::sort(keys.begin(), keys.end());
+            keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+            uint32_t lg = o.bitmap_log2;
+            if (lg == 0) lg = std::min<uint32_t>(19, std::max<uint32_t>(12, ceil_log2(keys.size()) + 8));
+            if (lg < 12 || lg > 19) {
+                err = "bitmap_log2 must be 12..19";
+                return GLOP_EINVAL;
+            }
+            c.qgram = q;
+            c.qmask = q == 4 ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+            c.stride = stride;
+            c.bitmap_log2 = lg;
+            c.filter_keys = keys.size();
+            c.bitmap.assign((1u << lg) / 32, 0);
+            for (uint32_t g : keys) {
+                uint32_t slot = glop_qgram_slot(g, lg);
+                c.bitmap[slot >> 5] |= 1u << (slot & 31);
+            }
+        } else {
+            if (o.stride > 1 || o.qgram || o.bitmap_log2) {
+                err = "stride/qgram/bitmap options need the q-gram filter";
+                return GLOP_EINVAL;
+            }
+            c.qgram = 0;
+            c.qmask = 0;
+            c.stride = 1;
+            c.bitmap_log2 = 12;
+            c.bitmap.assign((1u << 12) / 32, 0);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while compiling the dictionary";
+        return GLOP_ENOMEM;
+    }
+    return GLOP_OK;
+}
+
+namespace {
+
+struct Found {
+    uint64_t offset;
+    uint32_t state;
+};
+
+// Walk from every start in [lo, hi); record (start, deepest terminal).
+void walk_range(const Compiled &c, const uint8_t *text, uint64_t len, uint64_t lo, uint64_t hi,
+                std::vector<Found> &found) {
+    const uint32_t C = c.num_classes;
+    for (uint64_t i = lo; i < hi; ++i) {
+        uint32_t s = 0, last = 0;
+        for (uint64_t p = i; p < len; ++p) {
+            uint32_t e = c.delta[(uint64_t)s * C + c.cls[text[p]]];
+            if (e == 0) break;
+            s = e & GLOP_STATE_MASK;
+            if (e & GLOP_TERM_BIT) last = s;
+        }
+        if (last) found.push_back({i, last});
+    }
+}
+
+}  // namespace
+
+int cpu_walk(const Compiled &c, const uint8_t *text, uint64_t len, glop_match_t *out,
+             uint64_t max_matches, uint64_t *counts, uint64_t *total, int threads) {
+    if ((len > 0 && !text) || (max_matches > 0 && !out) || (c.num_patterns > 0 && !counts))
+        return GLOP_EINVAL;
+    if (counts) std::memset(counts, 0, sizeof(uint64_t) * c.num_patterns);
+    uint64_t emitted = 0;
+    if (c.num_patterns > 0 && len > 0) {
+        if (threads < 1) threads = 1;
+        if ((uint64_t)threads > len) threads = (int)len;
+        std::vector<std::vector<Found>> parts(threads);
+        try {
+            std::vector<std::thread> pool;
+            for (int t = 1; t < threads; ++t)
+                pool.emplace_back(walk_range, std::cref(c), text, len, len * t / threads, len * (t + 1) / threads,
+                                  std::ref(parts[t]));
+            walk_range(c, text, len, 0, len / threads, parts[0]);
+            for (auto &th : pool) th.join();
+        } catch (const std::exception &) {
+            return GLOP_ENOMEM;
+        }
+        for (const auto &part : parts)
+            for (const Found &f : part) {
+                uint32_t first = c.term[2 * f.state], cnt = c.term[2 * f.state + 1];
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    uint32_t id = c.outids[first + k];
+                    counts[id] += 1;
+                    if (emitted < max_matches) out[emitted] = glop_match_t{f.offset, id, 0};
+                    ++emitted;
+                }
+            }
+    }
+    if (total) *total = emitted;
+    return GLOP_OK;
+}
+
+}  // namespace glop

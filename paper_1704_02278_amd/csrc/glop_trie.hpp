@@ -1,0 +1,35 @@
+// Host-side compiler of the failureless trie and its device tables.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "glop.h"
+
+namespace glop {
+
+struct Compiled {
+    uint32_t num_patterns = 0;
+    uint32_t min_len = 0, max_len = 0;
+    uint32_t num_classes = 1;
+    uint8_t cls[256] = {};
+    uint32_t num_states = 1;
+    std::vector<uint32_t> delta;   // num_states * num_classes
+    std::vector<uint32_t> term;    // 2 * num_states
+    std::vector<uint32_t> outids;  // output lists
+    int32_t filter = GLOP_FILTER_NONE;
+    uint32_t qgram = 0, qmask = 0, stride = 1, bitmap_log2 = 12;
+    uint64_t filter_keys = 0;
+    std::vector<uint32_t> bitmap;  // 2^bitmap_log2 bits
+};
+
+// Returns GLOP_OK or an error code with `err` set.
+int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
+            const glop_build_opts *opts, Compiled &out, std::string &err);
+
+// CPU failureless-trie walk over a compiled dictionary (timing baseline).
+int cpu_walk(const Compiled &c, const uint8_t *text, uint64_t len, glop_match_t *out,
+             uint64_t max_matches, uint64_t *counts, uint64_t *total, int threads);
+
+}  // namespace glop

@@ -1,0 +1,65 @@
+"""Helpers for the GPU parity tests: run the HIP path, compare with the oracle."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+import paper_1704_02278_amd as glop
+
+
+def say(*parts):
+    print("[case]", *parts, flush=True)
+    sys.stdout.flush()
+
+
+def variants_for(patterns):
+    """Build options valid for this dictionary (every one must give the same result)."""
+    out = [dict()]
+    if patterns:
+        minlen = min(len(p) for p in patterns)
+        out.append(dict(filter=glop.GLOP_FILTER_NONE))
+        out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1))
+        if minlen >= 7:
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4))
+        if minlen >= 2:
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=1, bitmap_log2=12))
+    return out
+
+
+def to_device(text, shift: int = 0) -> torch.Tensor:
+    """Upload text so that its first byte sits `shift` bytes past a 256-byte boundary."""
+    arr = np.frombuffer(bytes(text), dtype=np.uint8) if not isinstance(text, np.ndarray) else text
+    buf = torch.empty(arr.size + 512, dtype=torch.uint8, device="cuda")
+    start = ((-buf.data_ptr()) % 256) + shift
+    t = buf[start:start + arr.size]
+    if arr.size:
+        t.copy_(torch.from_numpy(np.ascontiguousarray(arr)))
+    return t
+
+
+def gpu_match(d: glop.Dict, text_dev: torch.Tensor, max_matches=None):
+    off, ids, counts, total = d.match(text_dev, max_matches=max_matches)
+    torch.cuda.synchronize()
+    return (off.cpu().numpy().astype(np.uint64), ids.cpu().numpy().astype(np.uint64),
+            counts.cpu().numpy().astype(np.uint64), int(total))
+
+
+def oracle_match(text, patterns, threads=None):
+    off, ids, counts, total = oracle.match(text, patterns, bucketed=True, threads=threads)
+    return off.astype(np.uint64), ids.astype(np.uint64), counts.astype(np.uint64), int(total)
+
+
+def assert_same(got, want, what=""):
+    g_off, g_ids, g_counts, g_total = got
+    w_off, w_ids, w_counts, w_total = want
+    assert g_total == w_total, f"{what}: total {g_total} != {w_total}"
+    assert np.array_equal(g_counts, w_counts), f"{what}: counts differ"
+    assert g_off.size == w_off.size, f"{what}: {g_off.size} records vs {w_off.size}"
+    if not (np.array_equal(g_off, w_off) and np.array_equal(g_ids, w_ids)):
+        bad = int(np.flatnonzero((g_off != w_off) | (g_ids != w_ids))[0])
+        raise AssertionError(f"{what}: first difference at record {bad}: gpu ({g_off[bad]}, {g_ids[bad]}) "
+                             f"oracle ({w_off[bad]}, {w_ids[bad]})")

@@ -1,0 +1,120 @@
+"""C-ABI library: exports, the trie compiler and argument errors (CPU only).
+
+The trie compiler is checked through ``glop_cpu_walk``, the failureless walk
+over the compiled tables on the host, against the oracle; no GPU is touched.
+"""
+
+import ctypes
+import random
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from brute import brute_matches
+from golden_io import load_examples
+
+ROOT = Path(__file__).resolve().parent.parent
+glop = pytest.importorskip("paper_1704_02278_amd", reason="libglop.so not built")
+
+
+def header_functions():
+    text = (ROOT / "include" / "glop.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(glop_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert "glop_build" in names and "glop_match" in names and len(names) >= 12
+    lib = ctypes.CDLL(str(glop.LIB_PATH))
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+    assert set(names) == set(glop.EXPORTED)
+
+
+def host_dict(patterns, **opts):
+    return glop.Dict(patterns, device=False, **opts)
+
+
+def test_hand_examples_through_compiled_trie():
+    for ex in load_examples():
+        d = host_dict(ex.patterns)
+        off, ids, counts, total = d.cpu_walk(ex.text)
+        assert list(zip(off.tolist(), ids.tolist())) == ex.matches, ex.name
+        assert counts.tolist() == ex.counts and total == len(ex.matches)
+
+
+def test_random_small_cases_against_brute_force():
+    rng = random.Random(99)
+    for _ in range(200):
+        alpha = b"abc"[: rng.randint(1, 3)]
+        pats = [bytes(rng.choice(alpha) for _ in range(rng.randint(1, 6))) for _ in range(rng.randint(1, 7))]
+        text = bytes(rng.choice(alpha) for _ in range(rng.randint(0, 200)))
+        want, want_counts = brute_matches(text, pats)
+        off, ids, counts, total = host_dict(pats).cpu_walk(text, threads=rng.randint(1, 4))
+        assert list(zip(off.tolist(), ids.tolist())) == want
+        assert counts.tolist() == want_counts and total == len(want)
+
+
+@pytest.mark.parametrize("name,n_bytes", [("tiny", None), ("medium", 2 << 20), ("large", 1 << 20)])
+def test_compiled_trie_matches_oracle_on_workloads(name, n_bytes):
+    pats, text, _ = synth.make_workload(name, n_bytes=n_bytes)
+    o_off, o_ids, o_counts, o_total = oracle.match(text, pats)
+    off, ids, counts, total = host_dict(pats).cpu_walk(text, threads=8)
+    assert total == o_total
+    assert np.array_equal(off, o_off.astype(np.uint64)) and np.array_equal(ids, o_ids.astype(np.uint64))
+    assert np.array_equal(counts, o_counts)
+
+
+def test_state_count_is_distinct_prefixes_plus_root():
+    pats = synth.gen_patterns(synth.WORKLOADS["medium"].patterns, 5, 77)
+    prefixes = {p[:k] for p in pats for k in range(1, len(p) + 1)}
+    info = host_dict(pats).info()
+    assert info["num_states"] == len(prefixes) + 1
+    assert info["num_classes"] == len({b for p in pats for b in p}) + 1
+    assert info["min_len"] == 8 and info["max_len"] <= 64
+    # medium dictionary: 4-byte q-grams probed at every aligned word
+    assert info["filter"] == glop.GLOP_FILTER_QGRAM and info["stride"] == 4 and info["qgram"] == 4
+
+
+def test_automatic_options():
+    assert host_dict([b"abcdefg"]).info()["stride"] == 4
+    assert host_dict([b"abcdef"]).info()["stride"] == 1
+    i = host_dict([b"ab", b"abcdef"]).info()
+    assert i["qgram"] == 2 and i["stride"] == 1
+    assert host_dict([]).info()["filter"] == glop.GLOP_FILTER_NONE
+
+
+def test_build_errors():
+    with pytest.raises(glop.GlopError) as e:
+        host_dict([b"abc", b""])
+    assert e.value.code == glop.GLOP_EINVAL
+    with pytest.raises(glop.GlopError) as e:
+        host_dict([b"x" * (glop.GLOP_MAX_PATTERN_LEN + 1)])
+    assert e.value.code == glop.GLOP_ETOOLONG
+    for bad in (dict(stride=4, qgram=4, filter=glop.GLOP_FILTER_QGRAM),  # needs length >= 7
+                dict(qgram=5, filter=glop.GLOP_FILTER_QGRAM),
+                dict(bitmap_log2=25, filter=glop.GLOP_FILTER_QGRAM),
+                dict(stride=4, filter=glop.GLOP_FILTER_NONE),
+                dict(filter=7)):
+        with pytest.raises(glop.GlopError) as e:
+            host_dict([b"abcd"], **bad)
+        assert e.value.code == glop.GLOP_EINVAL
+
+
+def test_match_on_host_only_handle_is_refused():
+    d = host_dict([b"abc"])
+    rc = glop.glop_match(d.handle, None, 0, None, 0, ctypes.c_void_p(8), None)
+    assert rc == glop.GLOP_ENODEV
+    rc = glop.glop_match(d.handle, None, 5, None, 0, ctypes.c_void_p(8), None)
+    assert rc == glop.GLOP_EINVAL  # NULL text with len > 0 is caught first
+
+
+def test_workspace_grows_with_length():
+    d = host_dict([b"abc"])
+    a, b = d.workspace_bytes(1 << 20), d.workspace_bytes(1 << 30)
+    assert 0 < a < b and b % 256 == 0

@@ -1,0 +1,141 @@
+"""HIP path vs the CPU oracle, bit-exact (needs an MI355X).
+
+Every case goes through the C-ABI (``glop_build_ex`` / ``glop_match_ws``) via
+the ctypes binding.  Sizes span several 8 KiB tiles with ragged tails; edge
+cases cover empty inputs, unaligned text, tile-boundary straddles, dense
+matches (the staging-overflow path), truncation and binary bytes.
+"""
+
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from brute import brute_matches
+from golden_io import load_examples
+
+pytestmark = pytest.mark.gpu
+
+glop = pytest.importorskip("paper_1704_02278_amd")
+from gpu_util import assert_same, gpu_match, oracle_match, say, to_device, variants_for  # noqa: E402
+
+
+def test_hand_examples_every_variant():
+    for ex in load_examples():
+        for opts in variants_for(ex.patterns):
+            say("hand", ex.name, opts)
+            d = glop.Dict(ex.patterns, **opts)
+            off, ids, counts, total = gpu_match(d, to_device(ex.text))
+            assert list(zip(off.tolist(), ids.tolist())) == ex.matches, (ex.name, opts)
+            assert counts.tolist() == ex.counts and total == len(ex.matches), (ex.name, opts)
+
+
+def test_random_small_cases_vs_brute_force():
+    rng = random.Random(4242)
+    for k in range(60):
+        alpha = b"abc"[: rng.randint(1, 3)]
+        pats = [bytes(rng.choice(alpha) for _ in range(rng.randint(1, 9))) for _ in range(rng.randint(1, 7))]
+        text = bytes(rng.choice(alpha) for _ in range(rng.randint(0, 3000)))
+        want, want_counts = brute_matches(text, pats)
+        for opts in variants_for(pats):
+            say("random", k, len(text), opts)
+            off, ids, counts, total = gpu_match(glop.Dict(pats, **opts), to_device(text, shift=k % 16))
+            assert list(zip(off.tolist(), ids.tolist())) == want, (k, opts)
+            assert counts.tolist() == want_counts and total == len(want), (k, opts)
+
+
+@pytest.mark.parametrize("name,n_bytes", [("tiny", None), ("medium", 48 << 20), ("large", 8 << 20)])
+def test_workload_parity(name, n_bytes):
+    pats, text, plants = synth.make_workload(name, n_bytes=n_bytes)
+    want = oracle_match(text, pats)
+    assert want[3] >= len(plants)
+    t = to_device(text)
+    for opts in variants_for(pats):
+        say("workload", name, text.size, opts)
+        assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"{name} {opts}")
+
+
+def test_unaligned_text_and_ragged_lengths():
+    pats, text, _ = synth.make_workload("tiny", n_bytes=200_000)
+    d = glop.Dict(pats)
+    for shift in range(16):
+        for n in (0, 1, 3, 4, 15, 16, 17, 1023, 1024, 1025, 8191, 8192, 8193, 8192 * 3 + 7, 200_000 - shift):
+            sub = text[shift:shift + n]
+            say("unaligned", shift, n)
+            assert_same(gpu_match(d, to_device(sub, shift=shift)), oracle_match(sub, pats), f"shift {shift} n {n}")
+
+
+def test_tile_boundary_straddles():
+    # One plant per 8 KiB tile, at every offset from 40 bytes before to 8 after
+    # the tile's end, so occurrences straddle wave-tile and round boundaries.
+    rng = np.random.default_rng(7)
+    tile = 8192
+    pats = [b"HISTORY-of-a-long-pattern-" + bytes([65 + k]) * (k + 1) for k in range(6)] + [b"HIS", b"ISTO"]
+    deltas = list(range(-40, 9))
+    text = rng.integers(0x61, 0x7B, size=tile * (len(deltas) + 2), dtype=np.uint8)
+    for m, dlt in enumerate(deltas, start=1):
+        p = pats[m % 6]
+        o = m * tile + dlt
+        text[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    want = oracle_match(text, pats)
+    for shift in (0, 5, 13):
+        for opts in variants_for(pats):
+            say("straddle", shift, opts)
+            assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text, shift=shift)), want, f"{opts}")
+
+
+def test_dense_matches_take_the_overflow_path():
+    pats = [b"a", b"aa", b"aaa", b"b"]
+    text = b"a" * 70_000 + b"b" + b"a" * 33
+    want = oracle_match(text, pats)
+    for opts in variants_for(pats):
+        say("dense", opts)
+        assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text)), want, f"dense {opts}")
+
+
+def test_truncation_keeps_sorted_prefix_and_full_counts():
+    pats, text, _ = synth.make_workload("tiny")
+    want = oracle_match(text, pats)
+    d = glop.Dict(pats)
+    t = to_device(text)
+    for cap in (0, 1, 7, want[3] - 1, want[3], want[3] + 5):
+        say("truncate", cap)
+        off, ids, counts, total = gpu_match(d, t, max_matches=cap)
+        k = min(cap, want[3])
+        assert total == want[3] and np.array_equal(counts, want[2])
+        assert np.array_equal(off, want[0][:k]) and np.array_equal(ids, want[1][:k])
+
+
+def test_empty_inputs():
+    say("empty")
+    d = glop.Dict([b"abc", b"de"])
+    off, ids, counts, total = gpu_match(d, to_device(b""))
+    assert total == 0 and off.size == 0 and counts.tolist() == [0, 0]
+    off, ids, counts, total = gpu_match(d, to_device(b"a"))  # shorter than every pattern
+    assert total == 0 and counts.tolist() == [0, 0]
+    e = glop.Dict([])
+    off, ids, counts, total = gpu_match(e, to_device(b"abcabc"))
+    assert total == 0 and off.size == 0
+
+
+def test_binary_bytes():
+    rng = np.random.default_rng(11)
+    text = rng.integers(0, 4, size=300_000, dtype=np.uint8) * np.uint8(85)  # 0x00 0x55 0xAA 0xFF
+    pats = [bytes(rng.integers(0, 4, size=int(L)) * 85) for L in rng.integers(1, 12, size=40)]
+    pats += [b"\x00\xff", b"\xff\xff\xff\xff\xff\xff\xff\xff", b"\x00"]
+    want = oracle_match(text, pats)
+    for opts in variants_for(pats):
+        say("binary", opts)
+        assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text, shift=3)), want, f"binary {opts}")
+
+
+def test_repeated_runs_are_identical():
+    pats, text, _ = synth.make_workload("medium", n_bytes=8 << 20)
+    d = glop.Dict(pats)
+    t = to_device(text)
+    first = gpu_match(d, t)
+    for k in range(5):
+        say("repeat", k)
+        assert_same(gpu_match(d, t), first, f"repeat {k}")
