@@ -123,7 +123,7 @@ def test_empty_inputs():
 def test_binary_bytes():
     rng = np.random.default_rng(11)
     text = rng.integers(0, 4, size=300_000, dtype=np.uint8) * np.uint8(85)  # 0x00 0x55 0xAA 0xFF
-    pats = [bytes(rng.integers(0, 4, size=int(L)) * 85) for L in rng.integers(1, 12, size=40)]
+    pats = [bytes((rng.integers(0, 4, size=int(L)) * 85).astype(np.uint8)) for L in rng.integers(1, 12, size=40)]
     pats += [b"\x00\xff", b"\xff\xff\xff\xff\xff\xff\xff\xff", b"\x00"]
     want = oracle_match(text, pats)
     for opts in variants_for(pats):
