@@ -81,6 +81,8 @@ typedef struct glop_dict *glop_handle_t;
  *               the shortest pattern length.
  *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
  *               resident in LDS).
+ *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram, both in one 32-bit
+ *               word of the bitmap (a blocked Bloom filter).
  */
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1
@@ -90,6 +92,7 @@ typedef struct {
     uint32_t stride;
     uint32_t qgram;
     uint32_t bitmap_log2;
+    uint32_t probe_bits;
 } glop_build_opts;
 
 /*
@@ -208,7 +211,7 @@ typedef struct {
     uint64_t table_bytes;    /* transition table size on the device */
     uint64_t outlist_ids;    /* total entries of the per-state output lists */
     int32_t filter;          /* GLOP_FILTER_NONE or GLOP_FILTER_QGRAM as chosen */
-    uint32_t stride, qgram, bitmap_log2;
+    uint32_t stride, qgram, bitmap_log2, probe_bits;
     uint64_t filter_keys;    /* distinct q-grams set in the bitmap */
     uint64_t device_bytes;   /* device memory held by the handle */
     int32_t device;          /* HIP device id, or -1 for a host-only handle */

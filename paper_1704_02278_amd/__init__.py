@@ -44,7 +44,7 @@ class glop_match_t(ctypes.Structure):
 
 class glop_build_opts(ctypes.Structure):
     _fields_ = [("filter", ctypes.c_int32), ("stride", ctypes.c_uint32), ("qgram", ctypes.c_uint32),
-                ("bitmap_log2", ctypes.c_uint32)]
+                ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32)]
 
 
 class glop_events_t(ctypes.Structure):
@@ -56,7 +56,8 @@ class glop_info_t(ctypes.Structure):
         ("num_patterns", ctypes.c_uint32), ("min_len", ctypes.c_uint32), ("max_len", ctypes.c_uint32),
         ("num_classes", ctypes.c_uint32), ("num_states", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("outlist_ids", ctypes.c_uint64), ("filter", ctypes.c_int32), ("stride", ctypes.c_uint32),
-        ("qgram", ctypes.c_uint32), ("bitmap_log2", ctypes.c_uint32), ("filter_keys", ctypes.c_uint64),
+        ("qgram", ctypes.c_uint32), ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32),
+        ("filter_keys", ctypes.c_uint64),
         ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
     ]
 
@@ -111,17 +112,17 @@ def _pattern_arrays(patterns):
     return keep, ptrs, lens, len(pats)
 
 
-def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0):
-    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2))
+def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0):
+    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits))
 
 
 class Dict:
     """A compiled dictionary on the current device (or host-only with ``device=False``)."""
 
     def __init__(self, patterns, *, device: bool = True, filter=GLOP_FILTER_AUTO, stride=0, qgram=0,
-                 bitmap_log2=0):
+                 bitmap_log2=0, probe_bits=0):
         keep, ptrs, lens, n = _pattern_arrays(patterns)
-        opts = _opts(filter, stride, qgram, bitmap_log2)
+        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits)
         fn = glop_build_ex if device else glop_compile
         h = fn(ctypes.cast(ptrs, _u8pp), lens, n, ctypes.byref(opts))
         if not h:

@@ -107,6 +107,7 @@ int upload(glop_dict *h) {
     d.qmask = c.qmask;
     d.stride = c.stride;
     d.bitmap_log2 = c.bitmap_log2;
+    d.probe_bits = c.probe_bits;
     d.filter = c.filter;
     return GLOP_OK;
 }
@@ -259,6 +260,7 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->stride = c.stride;
     out->qgram = c.qgram;
     out->bitmap_log2 = c.bitmap_log2;
+    out->probe_bits = c.probe_bits;
     out->filter_keys = c.filter_keys;
     out->device_bytes = h->blob_bytes;
     out->device = h->blob ? h->device : -1;

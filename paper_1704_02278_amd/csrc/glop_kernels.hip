@@ -54,6 +54,7 @@ struct ScanParams {
     uint64_t valid_end;    // x < valid_end (and x >= head) can start a pattern
     uint64_t ntiles;
     uint64_t tiles_per_wg;
+    uint64_t int_begin, int_end;  // tiles in [int_begin, int_end) lie inside the text with their extra word
     uint32_t bm_bytes;     // bitmap bytes staged in LDS (0 without filter)
     uint64_t *tile_rec;    // records per tile
     uint32_t *tile_nm;     // matched starts per tile
@@ -121,9 +122,14 @@ __device__ __forceinline__ uint32_t load4(const ScanParams &P, uint64_t x) {
     return w;
 }
 
-__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t lg) {
-    uint32_t slot = glop_qgram_slot(g & qmask, lg);
-    return (bm[slot >> 5] >> (slot & 31)) & 1u;
+// Blocked Bloom probe: 1 if every probe bit of q-gram g is set in its word.
+template <int K>
+__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t wsh) {
+    const uint32_t h = glop_qgram_hash(g & qmask);
+    const uint32_t w = bm[glop_bloom_word(h, wsh)];
+    uint32_t hit = (w >> glop_bloom_bit1(h, wsh)) & 1u;
+    if (K == 2) hit &= (w >> glop_bloom_bit2(h, wsh)) & 1u;
+    return hit;
 }
 
 // Offsets x .. x+15 that may start a pattern: head <= x+u < valid_end.
@@ -137,17 +143,38 @@ __device__ __forceinline__ uint32_t valid_mask16(const ScanParams &P, uint64_t x
 }
 
 // The failureless walk from text offset i (Section 5): follow goto edges while
-// they exist; return the deepest terminal state passed (0 = none).
+// they exist; return the deepest terminal state passed (0 = none).  Text bytes
+// come 8 at a time from aligned loads.
 __device__ __forceinline__ uint32_t walk(const ScanParams &P, const uint8_t *cls, uint64_t i) {
     const uint32_t C = P.d.num_classes;
     const uint32_t *delta = P.d.delta;
     uint32_t s = 0, last = 0;
-    for (uint64_t p = i; p < P.len; ++p) {
-        uint32_t c = cls[P.text[p]];
-        uint32_t e = delta[(uint64_t)s * C + c];
+    uint64_t x = i + P.head;  // coordinate of the current byte
+    uint64_t win = 0;
+    uint32_t have = 0;
+    while (x < P.span_end) {
+        if (have == 0) {
+            const uint64_t xa = x & ~7ull;
+            if (xa >= P.head && xa + 8 <= P.span_end) {
+                win = *reinterpret_cast<const uint64_t *>(P.abase + xa);
+            } else {
+                win = 0;
+                for (int k = 0; k < 8; ++k) {
+                    const uint64_t y = xa + k;
+                    if (y >= P.head && y < P.span_end) win |= (uint64_t)P.abase[y] << (8 * k);
+                }
+            }
+            win >>= 8 * (x - xa);
+            have = 8 - (uint32_t)(x - xa);
+        }
+        const uint32_t c = cls[win & 0xFFu];
+        win >>= 8;
+        --have;
+        const uint32_t e = delta[(uint64_t)s * C + c];
         if (e == 0) break;
         s = e & GLOP_STATE_MASK;
         if (e & GLOP_TERM_BIT) last = s;
+        ++x;
     }
     return last;
 }
@@ -203,95 +230,139 @@ struct DirectSink {
     __device__ __forceinline__ void finish(const ScanParams &, uint64_t) {}
 };
 
-// One wave processes tile t: load, filter, queue, walk.  Returns the tile's
-// record count as seen by the sink (wave-uniform).
-template <int STRIDE, bool FILTER, class Sink>
-__device__ __forceinline__ void scan_tile(const ScanParams &P, uint64_t t, const uint32_t *bm,
-                                          const uint8_t *cls, uint16_t *queue, Sink &sink) {
+// A wave's tile in registers: 16 bytes per lane per round, plus the first
+// word after the tile (for the probes of the tile's last offsets).
+struct TileRegs {
+    uint4 v[kRounds];
+    uint32_t extra;
+};
+
+// Any tile: every byte checked against the text bounds.
+template <bool FILTER>
+__device__ __forceinline__ void load_tile(const ScanParams &P, uint64_t t, TileRegs &r) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t x0 = t * (uint64_t)kTileBytes;
-    const uint32_t qmask = P.d.qmask, lg = P.d.bitmap_log2;
-
-    uint4 v[kRounds];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) v[r] = load16(P, x0 + (uint64_t)r * kRoundBytes + lane * 16u);
-    const uint32_t extra = FILTER ? load4(P, x0 + kTileBytes) : 0u;
+    for (int k = 0; k < kRounds; ++k) r.v[k] = load16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+    r.extra = FILTER ? load4(P, x0 + kTileBytes) : 0u;
+}
 
-    // Stride 4: probe bit of each aligned word, 4 per round, packed.
-    uint32_t pbits = 0, extra_bit = 0;
+// Interior tile (int_begin <= t < int_end): plain coalesced 16-byte loads.
+template <bool FILTER>
+__device__ __forceinline__ void load_tile_interior(const ScanParams &P, uint64_t t, TileRegs &r) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint8_t *p = P.abase + t * (uint64_t)kTileBytes + lane * 16u;
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) r.v[k] = *reinterpret_cast<const uint4 *>(p + k * kRoundBytes);
+    r.extra = FILTER ? *reinterpret_cast<const uint32_t *>(P.abase + (t + 1) * (uint64_t)kTileBytes) : 0u;
+}
+
+// Candidate offsets of tile t: bit u of round k's 16-bit mask (word k/2,
+// half k%2) marks offset x0 + k*1024 + lane*16 + u as not ruled out.
+template <int STRIDE, bool FILTER, int K>
+__device__ __forceinline__ void tile_masks(const ScanParams &P, uint64_t t, const TileRegs &r,
+                                           const uint32_t *bm, uint32_t (&m)[kRounds / 2]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t x0 = t * (uint64_t)kTileBytes;
+    const uint32_t qmask = P.d.qmask, wsh = glop_word_shift(P.d.bitmap_log2);
+#pragma unroll
+    for (int k = 0; k < kRounds / 2; ++k) m[k] = 0;
+
     if (FILTER && STRIDE == 4) {
+        // One probe per aligned word; offset x maps to the word at roundup4(x):
+        // the lane's offset 0 to its word 0, 1..4 to word 1, 5..8 to word 2,
+        // 9..12 to word 3, 13..15 to the next lane's word 0.
+        uint32_t pbits = 0;
 #pragma unroll
-        for (int r = 0; r < kRounds; ++r) {
-            pbits |= probe(bm, v[r].x, qmask, lg) << (4 * r);
-            pbits |= probe(bm, v[r].y, qmask, lg) << (4 * r + 1);
-            pbits |= probe(bm, v[r].z, qmask, lg) << (4 * r + 2);
-            pbits |= probe(bm, v[r].w, qmask, lg) << (4 * r + 3);
+        for (int k = 0; k < kRounds; ++k) {
+            pbits |= probe<K>(bm, r.v[k].x, qmask, wsh) << (4 * k);
+            pbits |= probe<K>(bm, r.v[k].y, qmask, wsh) << (4 * k + 1);
+            pbits |= probe<K>(bm, r.v[k].z, qmask, wsh) << (4 * k + 2);
+            pbits |= probe<K>(bm, r.v[k].w, qmask, wsh) << (4 * k + 3);
         }
-        extra_bit = probe(bm, extra, qmask, lg);
-    }
-    const uint32_t pbits_lane0 = __builtin_amdgcn_readfirstlane(pbits);
-
-    uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+        const uint32_t extra_bit = probe<K>(bm, r.extra, qmask, wsh);
+        const uint32_t pbits_lane0 = __builtin_amdgcn_readfirstlane(pbits);
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-        const uint64_t xl = x0 + (uint64_t)r * kRoundBytes + lane * 16u;
-        uint32_t mask;
-        if (!FILTER) {
-            mask = 0xFFFFu;
-        } else if (STRIDE == 4) {
-            // Offset x maps to the aligned word at roundup4(x): offsets 1..4 of
-            // the lane to word 1, ..., 13..15 to the next lane's word 0.
-            const uint64_t b0 = __ballot((pbits >> (4 * r)) & 1u);
+        for (int k = 0; k < kRounds; ++k) {
+            const uint64_t b0 = __ballot((pbits >> (4 * k)) & 1u);
             uint32_t nb0;
             if (lane < kWave - 1) nb0 = (uint32_t)(b0 >> (lane + 1)) & 1u;
-            else nb0 = (r + 1 < kRounds) ? ((pbits_lane0 >> (4 * (r + 1))) & 1u) : extra_bit;
-            const uint32_t pb = (pbits >> (4 * r)) & 0xFu;
-            mask = (pb & 1u) | (((pb >> 1) & 1u) * 0x001Eu) | (((pb >> 2) & 1u) * 0x01E0u) |
-                   (((pb >> 3) & 1u) * 0x1E00u) | (nb0 * 0xE000u);
-        } else {
-            // Stride 1: the q-gram at each of the lane's 16 offsets.
-            // Bytes 16..19 of the lane = the next lane's first word; for the
-            // last lane, the next round's lane 0 (read wave-wide, before any
-            // divergence) or the word after the tile.
-            const uint32_t next0 =
-                (r + 1 < kRounds) ? __builtin_amdgcn_readfirstlane(v[(r + 1) % kRounds].x) : extra;
-            uint32_t nx = __shfl_down(v[r].x, 1);
-            if (lane == kWave - 1) nx = next0;
-            const uint32_t w[5] = {v[r].x, v[r].y, v[r].z, v[r].w, nx};
-            mask = 0;
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
-                                           : w[u >> 2];
-                mask |= probe(bm, g, qmask, lg) << u;
-            }
+            else nb0 = (k + 1 < kRounds) ? ((pbits_lane0 >> (4 * (k + 1))) & 1u) : extra_bit;
+            const uint32_t pb = (pbits >> (4 * k)) & 0xFu;
+            uint32_t mask = (pb & 1u) | (((pb >> 1) & 1u) * 0x001Eu) | (((pb >> 2) & 1u) * 0x01E0u) |
+                            (((pb >> 3) & 1u) * 0x1E00u) | (nb0 * 0xE000u);
+            mask &= valid_mask16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+            m[k / 2] |= mask << (16 * (k % 2));
         }
-        mask &= valid_mask16(P, xl);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRounds; ++k) {
+            uint32_t mask = 0xFFFFu;
+            if (FILTER) {
+                // One probe per offset: the q-gram starting there.  Bytes 16..19
+                // of the lane are the next lane's first word; for the last lane,
+                // the next round's lane 0 (read wave-wide, before any
+                // divergence) or the word after the tile.
+                const uint32_t next0 =
+                    (k + 1 < kRounds) ? __builtin_amdgcn_readfirstlane(r.v[(k + 1) % kRounds].x) : r.extra;
+                uint32_t nx = __shfl_down(r.v[k].x, 1);
+                if (lane == kWave - 1) nx = next0;
+                const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
+                mask = 0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const uint32_t g =
+                        (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3) : w[u >> 2];
+                    mask |= probe<K>(bm, g, qmask, wsh) << u;
+                    if ((u & 3) == 3) {
+                        // Finish these probes here; left alone, the compiler
+                        // defers the bit tests and spills every hash and word.
+                        __asm__ volatile("" : "+v"(mask));
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+            mask &= valid_mask16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+            m[k / 2] |= mask << (16 * (k % 2));
+            // Keep rounds apart: interleaving all 128 probes of the tile costs
+            // more registers than the wave has.
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
 
-        // Ordered append of this round's candidates to the ring.
-        if (__ballot(mask != 0) != 0) {
-            const uint32_t c = (uint32_t)__popc(mask);
-            uint32_t pre = 0, tot = 0;
+// Append tile t's candidates to the wave's LDS ring in offset order and walk
+// them 64 at a time (one per lane); the sink receives each batch's results.
+template <class Sink>
+__device__ __forceinline__ void walk_candidates(const ScanParams &P, uint64_t t, const uint32_t (&m)[kRounds / 2],
+                                                const uint8_t *cls, uint16_t *queue, Sink &sink) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t x0 = t * (uint64_t)kTileBytes;
+    uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
 #pragma unroll
-            for (int b = 0; b < 5; ++b) {
-                const uint64_t bal = __ballot((c >> b) & 1u);
-                pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
-                tot += (uint32_t)__popcll(bal) << b;
-            }
-            uint32_t pos = qtail + pre;
-            uint32_t mm = mask;
-            const uint32_t base_off = (uint32_t)r * kRoundBytes + lane * 16u;
-            while (mm) {
-                const uint32_t u = (uint32_t)__builtin_ctz(mm);
-                mm &= mm - 1u;
-                queue[(pos++) & (kQueueCap - 1)] = (uint16_t)(base_off + u);
-            }
-            qtail += tot;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = 0; k < kRounds; ++k) {
+        const uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+        if (__ballot(mask != 0) == 0) continue;
+        const uint32_t c = (uint32_t)__popc(mask);
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            const uint64_t bal = __ballot((c >> b) & 1u);
+            pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
+            tot += (uint32_t)__popcll(bal) << b;
         }
-        // Walk full batches: one candidate per lane.
+        uint32_t pos = qtail + pre;
+        uint32_t mm = mask;
+        const uint32_t base_off = (uint32_t)k * kRoundBytes + lane * 16u;
+        while (mm) {
+            const uint32_t u = (uint32_t)__builtin_ctz(mm);
+            mm &= mm - 1u;
+            queue[(pos++) & (kQueueCap - 1)] = (uint16_t)(base_off + u);
+        }
+        qtail += tot;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         while (qtail - qhead >= (uint32_t)kWave) {
             const uint32_t off = queue[(qhead + lane) & (kQueueCap - 1)];
             const uint32_t last = walk(P, cls, x0 + off - P.head);
@@ -299,7 +370,6 @@ __device__ __forceinline__ void scan_tile(const ScanParams &P, uint64_t t, const
             qhead += kWave;
         }
     }
-    // Last partial batch.
     if (qtail != qhead) {
         const uint32_t k = qtail - qhead;
         const bool act = lane < k;
@@ -323,7 +393,7 @@ __device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, 
         reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
 }
 
-template <int STRIDE, bool FILTER>
+template <int STRIDE, bool FILTER, int K>
 __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint64_t wsum[kWaves];
@@ -342,9 +412,28 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
     const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
     uint64_t total = 0;
-    for (uint64_t t = tb + wave; t < te; t += kWaves) {
+    // Interior tiles, pipelined: once a tile's candidate masks are known its
+    // bytes are dead, so the next tile's loads go out before this tile's walks.
+    const uint64_t ib = max(tb, P.int_begin), ie = min(te, P.int_end);
+    TileRegs r;
+    uint64_t t = ib + wave;
+    if (t < ie) load_tile_interior<FILTER>(P, t, r);
+    for (; t < ie; t += kWaves) {
+        uint32_t m[kRounds / 2];
+        tile_masks<STRIDE, FILTER, K>(P, t, r, bm, m);
+        if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
         StageSink sink;
-        scan_tile<STRIDE, FILTER>(P, t, bm, cls, queues + wave * kQueueCap, sink);
+        walk_candidates(P, t, m, cls, queues + wave * kQueueCap, sink);
+        total += sink.rec;
+    }
+    // Edge tiles (the first and last of the text): bounds-checked loads.
+    for (uint64_t e = tb + wave; e < te; e += kWaves) {
+        if (e >= ib && e < ie) continue;
+        load_tile<FILTER>(P, e, r);
+        uint32_t m[kRounds / 2];
+        tile_masks<STRIDE, FILTER, K>(P, e, r, bm, m);
+        StageSink sink;
+        walk_candidates(P, e, m, cls, queues + wave * kQueueCap, sink);
         total += sink.rec;
     }
     if (lane == 0) wsum[wave] = total;
@@ -385,7 +474,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
     return excl;
 }
 
-template <int STRIDE, bool FILTER>
+template <int STRIDE, bool FILTER, int K>
 __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitParams E) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint64_t scan_sh[kWaves + 1];
@@ -451,8 +540,13 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         }
         __syncthreads();
         for (uint32_t o = wave; o < n_over; o += kWaves) {
+            const uint64_t ot = over_tile[o];
+            TileRegs r;
+            load_tile<FILTER>(P, ot, r);
+            uint32_t m[kRounds / 2];
+            tile_masks<STRIDE, FILTER, K>(P, ot, r, bm, m);
             DirectSink sink{&E, over_base[o]};
-            scan_tile<STRIDE, FILTER>(P, over_tile[o], bm, cls, queues + wave * kQueueCap, sink);
+            walk_candidates(P, ot, m, cls, queues + wave * kQueueCap, sink);
         }
         __syncthreads();
         base += chunk_total;
@@ -489,7 +583,7 @@ Geometry geometry(uint64_t len, int num_cus) {
     return g;
 }
 
-template <int STRIDE, bool FILTER>
+template <int STRIDE, bool FILTER, int K>
 hipError_t launch_pair(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t stream,
                        const glop_events_t *ev) {
     const size_t lds = (size_t)P.bm_bytes + 256 + kQueueBytes;
@@ -497,26 +591,26 @@ hipError_t launch_pair(const ScanParams &P, const EmitParams &E, uint32_t grid, 
         hipError_t e = hipEventRecord((hipEvent_t)ev->scan_begin, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER>), dim3(grid), dim3(kBlock), lds, stream, P);
+    hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K>), dim3(grid), dim3(kBlock), lds, stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && ev->scan_end) {
         e = hipEventRecord((hipEvent_t)ev->scan_end, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER>), dim3(grid), dim3(kBlock), lds, stream, P, E);
+    hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K>), dim3(grid), dim3(kBlock), lds, stream, P, E);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && ev->emit_end) e = hipEventRecord((hipEvent_t)ev->emit_end, stream);
     return e;
 }
 
-template <int STRIDE, bool FILTER>
+template <int STRIDE, bool FILTER, int K>
 hipError_t set_lds_limit(int bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -526,9 +620,11 @@ uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_c
 
 hipError_t prepare_kernels() {
     const int bytes = (1 << 19) / 8 + 256 + (int)kQueueBytes;
-    hipError_t e = set_lds_limit<1, false>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<1, true>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<4, true>(bytes);
+    hipError_t e = set_lds_limit<1, false, 1>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<1, true, 1>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<1, true, 2>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<4, true, 1>(bytes);
+    if (e == hipSuccess) e = set_lds_limit<4, true, 2>(bytes);
     return e;
 }
 
@@ -557,6 +653,8 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     P.valid_end = P.head + a.len - d.min_len + 1;
     P.ntiles = g.ntiles;
     P.tiles_per_wg = g.tiles_per_wg;
+    P.int_begin = P.head ? 1 : 0;
+    P.int_end = P.span_end >= 4 ? (P.span_end - 4) / kTileBytes : 0;
     P.bm_bytes = d.filter == GLOP_FILTER_QGRAM ? (1u << d.bitmap_log2) / 8 : 0u;
     uint8_t *ws = static_cast<uint8_t *>(a.workspace);
     P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);
@@ -565,9 +663,13 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     P.wgsum = reinterpret_cast<uint64_t *>(ws + g.off_wgsum);
     P.counts = a.counts;
     EmitParams E{a.out, a.max_matches, a.total};
-    if (d.filter != GLOP_FILTER_QGRAM) return launch_pair<1, false>(P, E, g.grid, stream, a.events);
-    if (d.stride == 4) return launch_pair<4, true>(P, E, g.grid, stream, a.events);
-    return launch_pair<1, true>(P, E, g.grid, stream, a.events);
+    if (d.filter != GLOP_FILTER_QGRAM) return launch_pair<1, false, 1>(P, E, g.grid, stream, a.events);
+    if (d.stride == 4) {
+        if (d.probe_bits == 2) return launch_pair<4, true, 2>(P, E, g.grid, stream, a.events);
+        return launch_pair<4, true, 1>(P, E, g.grid, stream, a.events);
+    }
+    if (d.probe_bits == 2) return launch_pair<1, true, 2>(P, E, g.grid, stream, a.events);
+    return launch_pair<1, true, 1>(P, E, g.grid, stream, a.events);
 }
 
 }  // namespace glop

@@ -18,10 +18,14 @@
 // only the deepest terminal it passed and emits that one list, which is already
 // in id order.
 //
-// Filter: a bitmap of 2^bitmap_log2 bits.  For every pattern p and every t in
-// [0, stride), the q bytes p[t .. t+q) (little-endian in a 32-bit word, zero
-// above q bytes) hash to a set bit.  A text position whose q-gram hashes to a
-// clear bit cannot be where any pattern's t-th q-gram sits.
+// Filter: a blocked Bloom filter of 2^bitmap_log2 bits, read as 32-bit
+// words.  For every pattern p and every t in [0, stride), the q bytes
+// p[t .. t+q) (little-endian in a 32-bit word, zero above q bytes) hash to
+// h = glop_qgram_hash(g); the top (bitmap_log2 - 5) bits of h pick a word and
+// the next 5 bits a bit b1 in it; with two probe bits, a second bit
+// b2 = b1 ^ (16 | next 4 bits) (always different from b1) is set in the same
+// word.  A text position whose word lacks any of its bits cannot be where any
+// pattern's t-th q-gram sits.
 #pragma once
 #include <stdint.h>
 
@@ -39,8 +43,14 @@
 // of g * floor(2^32 / phi) spread consecutive and structured keys well.
 GLOP_HD uint32_t glop_qgram_hash(uint32_t g) { return g * 0x9E3779B1u; }
 
-GLOP_HD uint32_t glop_qgram_slot(uint32_t g, uint32_t bitmap_log2) {
-    return glop_qgram_hash(g) >> (32u - bitmap_log2);
+// Right shift that leaves the word index of h (bitmap_log2 in 12..28).
+GLOP_HD uint32_t glop_word_shift(uint32_t bitmap_log2) { return 37u - bitmap_log2; }
+
+// Word index and the probe-bit mask of h (probe_bits 1 or 2).
+GLOP_HD uint32_t glop_bloom_word(uint32_t h, uint32_t wsh) { return h >> wsh; }
+GLOP_HD uint32_t glop_bloom_bit1(uint32_t h, uint32_t wsh) { return (h >> (wsh - 5u)) & 31u; }
+GLOP_HD uint32_t glop_bloom_bit2(uint32_t h, uint32_t wsh) {
+    return glop_bloom_bit1(h, wsh) ^ (16u | ((h >> (wsh - 9u)) & 15u));
 }
 
 struct GlopDevDict {
@@ -53,6 +63,6 @@ struct GlopDevDict {
     uint32_t num_states;
     uint32_t num_patterns;
     uint32_t min_len, max_len;
-    uint32_t qgram, qmask, stride, bitmap_log2;
+    uint32_t qgram, qmask, stride, bitmap_log2, probe_bits;
     int32_t filter;  // GLOP_FILTER_NONE or GLOP_FILTER_QGRAM
 };

@@ -195,19 +195,28 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
                 err = "bitmap_log2 must be 12..19";
                 return GLOP_EINVAL;
             }
+            uint32_t k = o.probe_bits ? o.probe_bits : 2u;
+            if (k != 1 && k != 2) {
+                err = "probe_bits must be 1 or 2";
+                return GLOP_EINVAL;
+            }
             c.qgram = q;
             c.qmask = q == 4 ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
             c.stride = stride;
             c.bitmap_log2 = lg;
+            c.probe_bits = k;
             c.filter_keys = keys.size();
             c.bitmap.assign((1u << lg) / 32, 0);
+            const uint32_t wsh = glop_word_shift(lg);
             for (uint32_t g : keys) {
-                uint32_t slot = glop_qgram_slot(g, lg);
-                c.bitmap[slot >> 5] |= 1u << (slot & 31);
+                const uint32_t h = glop_qgram_hash(g);
+                uint32_t bits = 1u << glop_bloom_bit1(h, wsh);
+                if (k == 2) bits |= 1u << glop_bloom_bit2(h, wsh);
+                c.bitmap[glop_bloom_word(h, wsh)] |= bits;
             }
         } else {
-            if (o.stride > 1 || o.qgram || o.bitmap_log2) {
-                err = "stride/qgram/bitmap options need the q-gram filter";
+            if (o.stride > 1 || o.qgram || o.bitmap_log2 || o.probe_bits) {
+                err = "stride/qgram/bitmap/probe options need the q-gram filter";
                 return GLOP_EINVAL;
             }
             c.qgram = 0;
