@@ -81,8 +81,8 @@ typedef struct glop_dict *glop_handle_t;
  *               the shortest pattern length.
  *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
  *               resident in LDS).
- *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram, both in one 32-bit
- *               word of the bitmap (a blocked Bloom filter).
+ *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram (independent
+ *               hashes: a Bloom filter with one or two hash functions).
  */
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1

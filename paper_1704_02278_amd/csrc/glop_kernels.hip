@@ -5,15 +5,17 @@
 //
 // scan  -- streams the text once from HBM.  Each wave owns 8 KiB tiles; a lane
 //          holds 16 consecutive bytes per 1 KiB round (one coalesced 16-byte
-//          load).  With the q-gram filter, the lane first probes an LDS bitmap
-//          that summarises the trie's first q levels: an offset whose q-gram
-//          (or, at stride 4, whose covering aligned 4-byte word) misses the
-//          bitmap cannot start any pattern and needs no walk.  This is the
-//          prefix-filter stage of Sections 2 and 5, made exact because every
-//          surviving offset is then walked through the full trie.  Surviving
-//          offsets are appended in order to a per-wave LDS ring and walked
+//          load).  With the q-gram filter, the lane first probes an LDS Bloom
+//          filter that summarises the trie's first q levels: an offset whose
+//          q-gram misses the filter cannot start any pattern and needs no walk.
+//          At stride 4 only aligned 4-byte words are probed; a word that hits
+//          stands for the four offsets whose patterns must contain it.  This is
+//          the prefix-filter stage of Sections 2 and 5, made exact because
+//          every surviving offset is then walked through the full trie.
+//          Survivors are appended in order to a per-wave LDS ring and walked
 //          64 at a time, one per lane, so walks run with full waves instead of
-//          the few divergent lanes Section 5 describes.  A walk reads bytes
+//          the few divergent lanes Section 5 describes.  A tile's next loads
+//          are issued as soon as its filter bits are known, before its walks.  A walk reads bytes
 //          past its tile as needed (the overlap of at least the longest
 //          pattern minus one byte that Section 4 requires between chunks).
 //          Each tile's matched starts (offset, deepest terminal state) are
@@ -40,9 +42,15 @@ constexpr int kBlock = kWave * kWaves;            // 1024 threads
 constexpr int kRoundBytes = kWave * 16;           // 1 KiB: 16 bytes per lane
 constexpr int kRounds = 8;                        // rounds per tile
 constexpr int kTileBytes = kRoundBytes * kRounds; // 8 KiB per wave tile
-constexpr int kQueueCap = 2048;                   // per-wave ring of candidate offsets (u16)
 constexpr uint32_t kStageCap = 16;                // staged matched starts per tile
-constexpr uint32_t kQueueBytes = kWaves * kQueueCap * 2;
+// Per-wave LDS rings (u16 entries).  Stride 1 queues offsets: at most 63 left
+// over plus 1024 from one round.  Stride 4 queues hit words: at most 15 left
+// over plus 256 from one round plus the word after the tile.
+constexpr uint32_t kRing1 = 2048;
+constexpr uint32_t kRing4 = 512;
+
+template <int STRIDE>
+constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
 
 struct ScanParams {
     GlopDevDict d;
@@ -69,10 +77,9 @@ struct EmitParams {
     uint64_t *total;
 };
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    return (1ull << lane) - 1ull;
-}
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
@@ -80,17 +87,37 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// Inclusive scan over the wave; returns the exclusive prefix, `total` = sum.
+// Exclusive scan over the wave; `total` = sum.
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
-    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t lane = lane_id();
     uint32_t incl = v;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
         uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+        if (lane >= (uint32_t)o) incl += y;
     }
     total = __shfl(incl, kWave - 1);
     return incl - v;
+}
+
+// Exclusive prefix over the wave of small counts c < 2^BITS, and the total.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t &total) {
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t bal = __ballot((c >> b) & 1u);
+        pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
+        tot += (uint32_t)__popcll(bal) << b;
+    }
+    total = tot;
+    return pre;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
@@ -99,9 +126,9 @@ __device__ __forceinline__ uint4 load16(const ScanParams &P, uint64_t x) {
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        uint64_t y = x + k;
-        uint32_t b = (y >= P.head && y < P.span_end) ? (uint32_t)P.abase[y] : 0u;
-        uint32_t sh = 8 * (k & 3);
+        const uint64_t y = x + k;
+        const uint32_t b = (y >= P.head && y < P.span_end) ? (uint32_t)P.abase[y] : 0u;
+        const uint32_t sh = 8 * (k & 3);
         if (k < 4) w0 |= b << sh;
         else if (k < 8) w1 |= b << sh;
         else if (k < 12) w2 |= b << sh;
@@ -116,20 +143,23 @@ __device__ __forceinline__ uint32_t load4(const ScanParams &P, uint64_t x) {
     uint32_t w = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        uint64_t y = x + k;
+        const uint64_t y = x + k;
         w |= ((y >= P.head && y < P.span_end) ? (uint32_t)P.abase[y] : 0u) << (8 * k);
     }
     return w;
 }
 
-// Blocked Bloom probe: 1 if every probe bit of q-gram g is set in its word.
-template <int K>
-__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t wsh) {
-    const uint32_t h = glop_qgram_hash(g & qmask);
-    const uint32_t w = bm[glop_bloom_word(h, wsh)];
-    uint32_t hit = (w >> glop_bloom_bit1(h, wsh)) & 1u;
-    if (K == 2) hit &= (w >> glop_bloom_bit2(h, wsh)) & 1u;
-    return hit;
+// Bloom probe: 1 if every probe bit of q-gram g is set.
+template <int K, bool Q4>
+__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t sh) {
+    if (!Q4) g &= qmask;
+    const uint32_t s1 = glop_hash1(g) >> sh;
+    uint32_t hit = bm[s1 >> 5] >> (s1 & 31);
+    if (K == 2) {
+        const uint32_t s2 = glop_hash2(g) >> sh;
+        hit &= bm[s2 >> 5] >> (s2 & 31);
+    }
+    return hit & 1u;
 }
 
 // Offsets x .. x+15 that may start a pattern: head <= x+u < valid_end.
@@ -140,6 +170,12 @@ __device__ __forceinline__ uint32_t valid_mask16(const ScanParams &P, uint64_t x
     hi = hi < 0 ? 0 : (hi > 16 ? 16 : hi);
     if (hi <= lo) return 0u;
     return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// Every offset of tile t can start a pattern (no masking needed).
+__device__ __forceinline__ bool tile_fully_valid(const ScanParams &P, uint64_t t) {
+    const uint64_t x0 = t * (uint64_t)kTileBytes;
+    return x0 >= P.head && x0 + kTileBytes <= P.valid_end;
 }
 
 // The failureless walk from text offset i (Section 5): follow goto edges while
@@ -195,7 +231,7 @@ struct StageSink {
         rec += wave_sum_u32(m ? P.d.term[2 * last + 1] : 0u);
     }
     __device__ __forceinline__ void finish(const ScanParams &P, uint64_t t) {
-        if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (lane_id() == 0) {
             P.tile_rec[t] = rec;
             P.tile_nm[t] = nm;
         }
@@ -240,145 +276,199 @@ struct TileRegs {
 // Any tile: every byte checked against the text bounds.
 template <bool FILTER>
 __device__ __forceinline__ void load_tile(const ScanParams &P, uint64_t t, TileRegs &r) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t x0 = t * (uint64_t)kTileBytes;
 #pragma unroll
-    for (int k = 0; k < kRounds; ++k) r.v[k] = load16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+    for (int k = 0; k < kRounds; ++k) r.v[k] = load16(P, x0 + (uint64_t)k * kRoundBytes + lane_id() * 16u);
     r.extra = FILTER ? load4(P, x0 + kTileBytes) : 0u;
 }
 
 // Interior tile (int_begin <= t < int_end): plain coalesced 16-byte loads.
 template <bool FILTER>
 __device__ __forceinline__ void load_tile_interior(const ScanParams &P, uint64_t t, TileRegs &r) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint8_t *p = P.abase + t * (uint64_t)kTileBytes + lane * 16u;
+    const uint8_t *p = P.abase + t * (uint64_t)kTileBytes + lane_id() * 16u;
 #pragma unroll
     for (int k = 0; k < kRounds; ++k) r.v[k] = *reinterpret_cast<const uint4 *>(p + k * kRoundBytes);
     r.extra = FILTER ? *reinterpret_cast<const uint32_t *>(P.abase + (t + 1) * (uint64_t)kTileBytes) : 0u;
 }
 
-// Candidate offsets of tile t: bit u of round k's 16-bit mask (word k/2,
-// half k%2) marks offset x0 + k*1024 + lane*16 + u as not ruled out.
-template <int STRIDE, bool FILTER, int K>
-__device__ __forceinline__ void tile_masks(const ScanParams &P, uint64_t t, const TileRegs &r,
-                                           const uint32_t *bm, uint32_t (&m)[kRounds / 2]) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+// ---- stride 4: one probe per aligned word ---------------------------------
+//
+// Offset x needs the word at roundup4(x) to hit (every pattern is at least
+// q + 3 bytes, so that word lies inside any occurrence starting at x, at
+// pattern position t = roundup4(x) - x in 0..3).  Bit 4k+w of the lane's
+// result is the word at x0 + k*1024 + lane*16 + 4w; `extra` is the word after
+// the tile (it serves the tile's last three offsets).
+template <int K, bool Q4>
+__device__ __forceinline__ void tile_hits4(const ScanParams &P, const TileRegs &r, const uint32_t *bm,
+                                           uint32_t &pbits, uint32_t &extra_bit) {
+    const uint32_t qmask = P.d.qmask, sh = 32u - P.d.bitmap_log2;
+    uint32_t b = 0;
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        b |= probe<K, Q4>(bm, r.v[k].x, qmask, sh) << (4 * k);
+        b |= probe<K, Q4>(bm, r.v[k].y, qmask, sh) << (4 * k + 1);
+        b |= probe<K, Q4>(bm, r.v[k].z, qmask, sh) << (4 * k + 2);
+        b |= probe<K, Q4>(bm, r.v[k].w, qmask, sh) << (4 * k + 3);
+        // Finish each round's probes in place (see tile_masks1).
+        __asm__ volatile("" : "+v"(b));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    pbits = b;
+    extra_bit = probe<K, Q4>(bm, r.extra, qmask, sh);
+}
+
+// Walk the four offsets of each queued hit word: lanes 4h..4h+3 take hit h's
+// offsets p-3, p-2, p-1, p, so a batch of 16 hits is in offset order.
+template <class Sink>
+__device__ __forceinline__ void walk_hit_batch(const ScanParams &P, uint64_t t, const uint8_t *cls,
+                                               const uint16_t *queue, uint32_t qhead, uint32_t n, Sink &sink) {
+    const uint32_t lane = lane_id();
     const uint64_t x0 = t * (uint64_t)kTileBytes;
-    const uint32_t qmask = P.d.qmask, wsh = glop_word_shift(P.d.bitmap_log2);
+    const uint32_t h = lane >> 2;
+    bool act = h < n;
+    const int32_t p = act ? (int32_t)queue[(qhead + h) & (kRing4 - 1)] : 0;
+    const int32_t off = p - 3 + (int32_t)(lane & 3);
+    const uint64_t x = x0 + (int64_t)off;
+    act = act && off >= 0 && off < kTileBytes && x >= P.head && x < P.valid_end;
+    const uint32_t last = act ? walk(P, cls, x - P.head) : 0u;
+    sink.batch(P, t, x0, act ? (uint32_t)off : 0u, last);
+}
+
+template <class Sink>
+__device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, uint32_t pbits, uint32_t extra_bit,
+                                           const uint8_t *cls, uint16_t *queue, Sink &sink) {
+    const uint32_t lane = lane_id();
+    if (__ballot(pbits != 0) != 0 || extra_bit) {
+        uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+#pragma unroll
+        for (int k = 0; k < kRounds; ++k) {
+            uint32_t bits = (pbits >> (4 * k)) & 0xFu;
+            if (__ballot(bits != 0) == 0) continue;
+            uint32_t tot;
+            uint32_t pos = qtail + wave_prefix_small<3>((uint32_t)__popc(bits), tot);
+            const uint32_t base = (uint32_t)k * kRoundBytes + lane * 16u;
+            while (bits) {
+                const uint32_t w = (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1u;
+                queue[(pos++) & (kRing4 - 1)] = (uint16_t)(base + 4u * w);
+            }
+            qtail += tot;
+            wave_lds_sync();
+            for (; qtail - qhead >= 16u; qhead += 16u) walk_hit_batch(P, t, cls, queue, qhead, 16u, sink);
+        }
+        if (extra_bit) {
+            if (lane == 0) queue[qtail & (kRing4 - 1)] = (uint16_t)kTileBytes;
+            qtail += 1;
+            wave_lds_sync();
+        }
+        for (; qtail != qhead;) {
+            const uint32_t n = min(16u, qtail - qhead);
+            walk_hit_batch(P, t, cls, queue, qhead, n, sink);
+            qhead += n;
+        }
+    }
+    sink.finish(P, t);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---- stride 1: one probe per offset (or none: walk every offset) ----------
+//
+// Bit u of round k's 16-bit mask (word k/2, half k%2) marks offset
+// x0 + k*1024 + lane*16 + u as not ruled out.
+template <bool FILTER, int K, bool Q4>
+__device__ __forceinline__ void tile_masks1(const ScanParams &P, uint64_t t, const TileRegs &r,
+                                            const uint32_t *bm, uint32_t (&m)[kRounds / 2]) {
+    const uint32_t lane = lane_id();
+    const uint64_t x0 = t * (uint64_t)kTileBytes;
+    const uint32_t qmask = P.d.qmask, sh = 32u - P.d.bitmap_log2;
+    const bool full = tile_fully_valid(P, t);
 #pragma unroll
     for (int k = 0; k < kRounds / 2; ++k) m[k] = 0;
-
-    if (FILTER && STRIDE == 4) {
-        // One probe per aligned word; offset x maps to the word at roundup4(x):
-        // the lane's offset 0 to its word 0, 1..4 to word 1, 5..8 to word 2,
-        // 9..12 to word 3, 13..15 to the next lane's word 0.
-        uint32_t pbits = 0;
 #pragma unroll
-        for (int k = 0; k < kRounds; ++k) {
-            pbits |= probe<K>(bm, r.v[k].x, qmask, wsh) << (4 * k);
-            pbits |= probe<K>(bm, r.v[k].y, qmask, wsh) << (4 * k + 1);
-            pbits |= probe<K>(bm, r.v[k].z, qmask, wsh) << (4 * k + 2);
-            pbits |= probe<K>(bm, r.v[k].w, qmask, wsh) << (4 * k + 3);
-        }
-        const uint32_t extra_bit = probe<K>(bm, r.extra, qmask, wsh);
-        const uint32_t pbits_lane0 = __builtin_amdgcn_readfirstlane(pbits);
+    for (int k = 0; k < kRounds; ++k) {
+        uint32_t mask = 0xFFFFu;
+        if (FILTER) {
+            // Bytes 16..19 of the lane are the next lane's first word; for the
+            // last lane, the next round's lane 0 (read wave-wide, before any
+            // divergence) or the word after the tile.
+            const uint32_t next0 =
+                (k + 1 < kRounds) ? __builtin_amdgcn_readfirstlane(r.v[(k + 1) % kRounds].x) : r.extra;
+            uint32_t nx = __shfl_down(r.v[k].x, 1);
+            if (lane == kWave - 1) nx = next0;
+            const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
+            mask = 0;
 #pragma unroll
-        for (int k = 0; k < kRounds; ++k) {
-            const uint64_t b0 = __ballot((pbits >> (4 * k)) & 1u);
-            uint32_t nb0;
-            if (lane < kWave - 1) nb0 = (uint32_t)(b0 >> (lane + 1)) & 1u;
-            else nb0 = (k + 1 < kRounds) ? ((pbits_lane0 >> (4 * (k + 1))) & 1u) : extra_bit;
-            const uint32_t pb = (pbits >> (4 * k)) & 0xFu;
-            uint32_t mask = (pb & 1u) | (((pb >> 1) & 1u) * 0x001Eu) | (((pb >> 2) & 1u) * 0x01E0u) |
-                            (((pb >> 3) & 1u) * 0x1E00u) | (nb0 * 0xE000u);
-            mask &= valid_mask16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
-            m[k / 2] |= mask << (16 * (k % 2));
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kRounds; ++k) {
-            uint32_t mask = 0xFFFFu;
-            if (FILTER) {
-                // One probe per offset: the q-gram starting there.  Bytes 16..19
-                // of the lane are the next lane's first word; for the last lane,
-                // the next round's lane 0 (read wave-wide, before any
-                // divergence) or the word after the tile.
-                const uint32_t next0 =
-                    (k + 1 < kRounds) ? __builtin_amdgcn_readfirstlane(r.v[(k + 1) % kRounds].x) : r.extra;
-                uint32_t nx = __shfl_down(r.v[k].x, 1);
-                if (lane == kWave - 1) nx = next0;
-                const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
-                mask = 0;
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const uint32_t g =
-                        (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3) : w[u >> 2];
-                    mask |= probe<K>(bm, g, qmask, wsh) << u;
-                    if ((u & 3) == 3) {
-                        // Finish these probes here; left alone, the compiler
-                        // defers the bit tests and spills every hash and word.
-                        __asm__ volatile("" : "+v"(mask));
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
+                                           : w[u >> 2];
+                mask |= probe<K, Q4>(bm, g, qmask, sh) << u;
+                if ((u & 3) == 3) {
+                    // Finish these probes here; left alone, the compiler
+                    // defers the bit tests and spills every hash and word.
+                    __asm__ volatile("" : "+v"(mask));
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            mask &= valid_mask16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
-            m[k / 2] |= mask << (16 * (k % 2));
-            // Keep rounds apart: interleaving all 128 probes of the tile costs
-            // more registers than the wave has.
-            __builtin_amdgcn_sched_barrier(0);
         }
+        if (!full) mask &= valid_mask16(P, x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+        m[k / 2] |= mask << (16 * (k % 2));
+        // Keep rounds apart: interleaving all probes of the tile costs more
+        // registers than the wave has.
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// Append tile t's candidates to the wave's LDS ring in offset order and walk
-// them 64 at a time (one per lane); the sink receives each batch's results.
 template <class Sink>
-__device__ __forceinline__ void walk_candidates(const ScanParams &P, uint64_t t, const uint32_t (&m)[kRounds / 2],
-                                                const uint8_t *cls, uint16_t *queue, Sink &sink) {
-    const uint32_t lane = threadIdx.x & (kWave - 1);
+__device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, const uint32_t (&m)[kRounds / 2],
+                                              const uint8_t *cls, uint16_t *queue, Sink &sink) {
+    const uint32_t lane = lane_id();
     const uint64_t x0 = t * (uint64_t)kTileBytes;
     uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
 #pragma unroll
     for (int k = 0; k < kRounds; ++k) {
-        const uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+        uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
         if (__ballot(mask != 0) == 0) continue;
-        const uint32_t c = (uint32_t)__popc(mask);
-        uint32_t pre = 0, tot = 0;
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            const uint64_t bal = __ballot((c >> b) & 1u);
-            pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
-            tot += (uint32_t)__popcll(bal) << b;
-        }
-        uint32_t pos = qtail + pre;
-        uint32_t mm = mask;
-        const uint32_t base_off = (uint32_t)k * kRoundBytes + lane * 16u;
-        while (mm) {
-            const uint32_t u = (uint32_t)__builtin_ctz(mm);
-            mm &= mm - 1u;
-            queue[(pos++) & (kQueueCap - 1)] = (uint16_t)(base_off + u);
+        uint32_t tot;
+        uint32_t pos = qtail + wave_prefix_small<5>((uint32_t)__popc(mask), tot);
+        const uint32_t base = (uint32_t)k * kRoundBytes + lane * 16u;
+        while (mask) {
+            const uint32_t u = (uint32_t)__builtin_ctz(mask);
+            mask &= mask - 1u;
+            queue[(pos++) & (kRing1 - 1)] = (uint16_t)(base + u);
         }
         qtail += tot;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        while (qtail - qhead >= (uint32_t)kWave) {
-            const uint32_t off = queue[(qhead + lane) & (kQueueCap - 1)];
+        wave_lds_sync();
+        for (; qtail - qhead >= (uint32_t)kWave; qhead += kWave) {
+            const uint32_t off = queue[(qhead + lane) & (kRing1 - 1)];
             const uint32_t last = walk(P, cls, x0 + off - P.head);
             sink.batch(P, t, x0, off, last);
-            qhead += kWave;
         }
     }
     if (qtail != qhead) {
-        const uint32_t k = qtail - qhead;
-        const bool act = lane < k;
-        const uint32_t off = act ? queue[(qhead + lane) & (kQueueCap - 1)] : 0u;
+        const uint32_t n = qtail - qhead;
+        const bool act = lane < n;
+        const uint32_t off = act ? queue[(qhead + lane) & (kRing1 - 1)] : 0u;
         const uint32_t last = act ? walk(P, cls, x0 + off - P.head) : 0u;
         sink.batch(P, t, x0, off, last);
     }
     sink.finish(P, t);
     __builtin_amdgcn_wave_barrier();
+}
+
+// Filter then walk one tile already in registers (no prefetch).
+template <int STRIDE, bool FILTER, int K, bool Q4, class Sink>
+__device__ __forceinline__ void scan_loaded_tile(const ScanParams &P, uint64_t t, const TileRegs &r,
+                                                 const uint32_t *bm, const uint8_t *cls, uint16_t *queue,
+                                                 Sink &sink) {
+    if constexpr (STRIDE == 4) {
+        uint32_t pbits, xb;
+        tile_hits4<K, Q4>(P, r, bm, pbits, xb);
+        walk_hits4(P, t, pbits, xb, cls, queue, sink);
+    } else {
+        uint32_t m[kRounds / 2];
+        tile_masks1<FILTER, K, Q4>(P, t, r, bm, m);
+        walk_offsets1(P, t, m, cls, queue, sink);
+    }
 }
 
 // Copy the bitmap and byte classes into LDS.
@@ -393,14 +483,14 @@ __device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, 
         reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
 }
 
-template <int STRIDE, bool FILTER, int K>
+template <int STRIDE, bool FILTER, int K, bool Q4>
 __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint64_t wsum[kWaves];
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + P.bm_bytes;
-    uint16_t *queues = reinterpret_cast<uint16_t *>(cls + 256);
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint16_t *queue = reinterpret_cast<uint16_t *>(cls + 256) + wave * ring_cap<STRIDE>();
 
     // Counts are accumulated by the emit kernel, which runs after this one.
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < P.d.num_patterns;
@@ -412,28 +502,33 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
     const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
     uint64_t total = 0;
-    // Interior tiles, pipelined: once a tile's candidate masks are known its
-    // bytes are dead, so the next tile's loads go out before this tile's walks.
+    // Interior tiles, pipelined: once a tile's filter bits are known its bytes
+    // are dead, so the next tile's loads go out before this tile's walks.
     const uint64_t ib = max(tb, P.int_begin), ie = min(te, P.int_end);
     TileRegs r;
     uint64_t t = ib + wave;
     if (t < ie) load_tile_interior<FILTER>(P, t, r);
     for (; t < ie; t += kWaves) {
-        uint32_t m[kRounds / 2];
-        tile_masks<STRIDE, FILTER, K>(P, t, r, bm, m);
-        if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
         StageSink sink;
-        walk_candidates(P, t, m, cls, queues + wave * kQueueCap, sink);
+        if constexpr (STRIDE == 4) {
+            uint32_t pbits, xb;
+            tile_hits4<K, Q4>(P, r, bm, pbits, xb);
+            if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
+            walk_hits4(P, t, pbits, xb, cls, queue, sink);
+        } else {
+            uint32_t m[kRounds / 2];
+            tile_masks1<FILTER, K, Q4>(P, t, r, bm, m);
+            if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
+            walk_offsets1(P, t, m, cls, queue, sink);
+        }
         total += sink.rec;
     }
     // Edge tiles (the first and last of the text): bounds-checked loads.
     for (uint64_t e = tb + wave; e < te; e += kWaves) {
         if (e >= ib && e < ie) continue;
         load_tile<FILTER>(P, e, r);
-        uint32_t m[kRounds / 2];
-        tile_masks<STRIDE, FILTER, K>(P, e, r, bm, m);
         StageSink sink;
-        walk_candidates(P, e, m, cls, queues + wave * kQueueCap, sink);
+        scan_loaded_tile<STRIDE, FILTER, K, Q4>(P, e, r, bm, cls, queue, sink);
         total += sink.rec;
     }
     if (lane == 0) wsum[wave] = total;
@@ -447,12 +542,12 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
 
 // Exclusive scan over the block (1024 threads); `total` = block sum.
 __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh, uint64_t &total) {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
     uint64_t incl = v;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
         uint64_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+        if (lane >= (uint32_t)o) incl += y;
     }
     if (lane == kWave - 1) sh[wave] = incl;
     __syncthreads();
@@ -462,7 +557,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
 #pragma unroll
         for (int o = 1; o < kWaves; o <<= 1) {
             uint64_t y = __shfl_up(wi, o);
-            if (lane >= o) wi += y;
+            if (lane >= (uint32_t)o) wi += y;
         }
         if (lane < kWaves) sh[lane] = wi - w;
         if (lane == kWaves - 1) sh[kWaves] = wi;
@@ -474,7 +569,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
     return excl;
 }
 
-template <int STRIDE, bool FILTER, int K>
+template <int STRIDE, bool FILTER, int K, bool Q4>
 __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitParams E) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint64_t scan_sh[kWaves + 1];
@@ -484,8 +579,8 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     __shared__ uint64_t over_base[kBlock];
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + P.bm_bytes;
-    uint16_t *queues = reinterpret_cast<uint16_t *>(cls + 256);
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint16_t *queue = reinterpret_cast<uint16_t *>(cls + 256) + wave * ring_cap<STRIDE>();
 
     const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
     const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
@@ -543,10 +638,8 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             const uint64_t ot = over_tile[o];
             TileRegs r;
             load_tile<FILTER>(P, ot, r);
-            uint32_t m[kRounds / 2];
-            tile_masks<STRIDE, FILTER, K>(P, ot, r, bm, m);
             DirectSink sink{&E, over_base[o]};
-            walk_candidates(P, ot, m, cls, queues + wave * kQueueCap, sink);
+            scan_loaded_tile<STRIDE, FILTER, K, Q4>(P, ot, r, bm, cls, queue, sink);
         }
         __syncthreads();
         base += chunk_total;
@@ -583,35 +676,47 @@ Geometry geometry(uint64_t len, int num_cus) {
     return g;
 }
 
-template <int STRIDE, bool FILTER, int K>
+template <int STRIDE>
+constexpr size_t dyn_lds(uint32_t bm_bytes) {
+    return (size_t)bm_bytes + 256 + (size_t)kWaves * ring_cap<STRIDE>() * 2;
+}
+
+template <int STRIDE, bool FILTER, int K, bool Q4>
 hipError_t launch_pair(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t stream,
                        const glop_events_t *ev) {
-    const size_t lds = (size_t)P.bm_bytes + 256 + kQueueBytes;
+    const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
     if (ev && ev->scan_begin) {
         hipError_t e = hipEventRecord((hipEvent_t)ev->scan_begin, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K>), dim3(grid), dim3(kBlock), lds, stream, P);
+    hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4>), dim3(grid), dim3(kBlock), lds, stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && ev->scan_end) {
         e = hipEventRecord((hipEvent_t)ev->scan_end, stream);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K>), dim3(grid), dim3(kBlock), lds, stream, P, E);
+    hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4>), dim3(grid), dim3(kBlock), lds, stream, P, E);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && ev->emit_end) e = hipEventRecord((hipEvent_t)ev->emit_end, stream);
     return e;
 }
 
-template <int STRIDE, bool FILTER, int K>
-hipError_t set_lds_limit(int bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K>),
+template <int STRIDE, bool FILTER, int K, bool Q4>
+hipError_t set_lds_limit() {
+    const int bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int STRIDE, int K, bool Q4>
+hipError_t launch_filtered(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
+                           const glop_events_t *ev) {
+    return launch_pair<STRIDE, true, K, Q4>(P, E, grid, s, ev);
 }
 
 }  // namespace
@@ -619,12 +724,15 @@ hipError_t set_lds_limit(int bytes) {
 uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus).bytes; }
 
 hipError_t prepare_kernels() {
-    const int bytes = (1 << 19) / 8 + 256 + (int)kQueueBytes;
-    hipError_t e = set_lds_limit<1, false, 1>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<1, true, 1>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<1, true, 2>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<4, true, 1>(bytes);
-    if (e == hipSuccess) e = set_lds_limit<4, true, 2>(bytes);
+    hipError_t e = set_lds_limit<1, false, 1, false>();
+    if (e == hipSuccess) e = set_lds_limit<1, true, 1, false>();
+    if (e == hipSuccess) e = set_lds_limit<1, true, 1, true>();
+    if (e == hipSuccess) e = set_lds_limit<1, true, 2, false>();
+    if (e == hipSuccess) e = set_lds_limit<1, true, 2, true>();
+    if (e == hipSuccess) e = set_lds_limit<4, true, 1, false>();
+    if (e == hipSuccess) e = set_lds_limit<4, true, 1, true>();
+    if (e == hipSuccess) e = set_lds_limit<4, true, 2, false>();
+    if (e == hipSuccess) e = set_lds_limit<4, true, 2, true>();
     return e;
 }
 
@@ -663,13 +771,20 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     P.wgsum = reinterpret_cast<uint64_t *>(ws + g.off_wgsum);
     P.counts = a.counts;
     EmitParams E{a.out, a.max_matches, a.total};
-    if (d.filter != GLOP_FILTER_QGRAM) return launch_pair<1, false, 1>(P, E, g.grid, stream, a.events);
+    const ScanParams &Pc = P;
+    if (d.filter != GLOP_FILTER_QGRAM) return launch_pair<1, false, 1, false>(Pc, E, g.grid, stream, a.events);
+    const bool q4 = d.qgram == 4;
+    const bool k2 = d.probe_bits == 2;
     if (d.stride == 4) {
-        if (d.probe_bits == 2) return launch_pair<4, true, 2>(P, E, g.grid, stream, a.events);
-        return launch_pair<4, true, 1>(P, E, g.grid, stream, a.events);
+        if (k2) return q4 ? launch_filtered<4, 2, true>(Pc, E, g.grid, stream, a.events)
+                          : launch_filtered<4, 2, false>(Pc, E, g.grid, stream, a.events);
+        return q4 ? launch_filtered<4, 1, true>(Pc, E, g.grid, stream, a.events)
+                  : launch_filtered<4, 1, false>(Pc, E, g.grid, stream, a.events);
     }
-    if (d.probe_bits == 2) return launch_pair<1, true, 2>(P, E, g.grid, stream, a.events);
-    return launch_pair<1, true, 1>(P, E, g.grid, stream, a.events);
+    if (k2) return q4 ? launch_filtered<1, 2, true>(Pc, E, g.grid, stream, a.events)
+                      : launch_filtered<1, 2, false>(Pc, E, g.grid, stream, a.events);
+    return q4 ? launch_filtered<1, 1, true>(Pc, E, g.grid, stream, a.events)
+              : launch_filtered<1, 1, false>(Pc, E, g.grid, stream, a.events);
 }
 
 }  // namespace glop

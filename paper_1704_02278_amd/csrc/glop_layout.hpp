@@ -18,14 +18,11 @@
 // only the deepest terminal it passed and emits that one list, which is already
 // in id order.
 //
-// Filter: a blocked Bloom filter of 2^bitmap_log2 bits, read as 32-bit
-// words.  For every pattern p and every t in [0, stride), the q bytes
-// p[t .. t+q) (little-endian in a 32-bit word, zero above q bytes) hash to
-// h = glop_qgram_hash(g); the top (bitmap_log2 - 5) bits of h pick a word and
-// the next 5 bits a bit b1 in it; with two probe bits, a second bit
-// b2 = b1 ^ (16 | next 4 bits) (always different from b1) is set in the same
-// word.  A text position whose word lacks any of its bits cannot be where any
-// pattern's t-th q-gram sits.
+// Filter: a Bloom filter of 2^bitmap_log2 bits.  For every pattern p and
+// every t in [0, stride), the q bytes p[t .. t+q) (little-endian in a 32-bit
+// word g, zero above q bytes) set bit glop_slot1(g) and, with two probe bits,
+// also bit glop_slot2(g).  A text position whose q-gram misses any of its bits
+// cannot be where any pattern's t-th q-gram sits.
 #pragma once
 #include <stdint.h>
 
@@ -39,19 +36,18 @@
 #define GLOP_TERM_BIT 0x80000000u
 #define GLOP_STATE_MASK 0x7FFFFFFFu
 
-// Multiplicative (Fibonacci) hashing, Knuth TAOCP vol. 3, 6.4: the top bits
-// of g * floor(2^32 / phi) spread consecutive and structured keys well.
-GLOP_HD uint32_t glop_qgram_hash(uint32_t g) { return g * 0x9E3779B1u; }
-
-// Right shift that leaves the word index of h (bitmap_log2 in 12..28).
-GLOP_HD uint32_t glop_word_shift(uint32_t bitmap_log2) { return 37u - bitmap_log2; }
-
-// Word index and the probe-bit mask of h (probe_bits 1 or 2).
-GLOP_HD uint32_t glop_bloom_word(uint32_t h, uint32_t wsh) { return h >> wsh; }
-GLOP_HD uint32_t glop_bloom_bit1(uint32_t h, uint32_t wsh) { return (h >> (wsh - 5u)) & 31u; }
-GLOP_HD uint32_t glop_bloom_bit2(uint32_t h, uint32_t wsh) {
-    return glop_bloom_bit1(h, wsh) ^ (16u | ((h >> (wsh - 9u)) & 15u));
+// Two hashes of a q-gram, each a 24x24-bit multiply-add (one full-rate
+// v_mad_u32_u24 on CDNA): the product mixes the low three bytes upwards and the
+// added key brings the fourth byte into the top bits that pick the slot.  The
+// second hash first rotates the key by one byte.  Slots are the top
+// bitmap_log2 bits.
+GLOP_HD uint32_t glop_hash1(uint32_t g) { return (g & 0xFFFFFFu) * 0x9E3779u + g; }
+GLOP_HD uint32_t glop_hash2(uint32_t g) {
+    const uint32_t r = (g >> 8) | (g << 24);
+    return (r & 0xFFFFFFu) * 0x85EBCAu + r;
 }
+GLOP_HD uint32_t glop_slot1(uint32_t g, uint32_t bitmap_log2) { return glop_hash1(g) >> (32u - bitmap_log2); }
+GLOP_HD uint32_t glop_slot2(uint32_t g, uint32_t bitmap_log2) { return glop_hash2(g) >> (32u - bitmap_log2); }
 
 struct GlopDevDict {
     const uint32_t *delta;   // num_states * num_classes

@@ -207,12 +207,13 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             c.probe_bits = k;
             c.filter_keys = keys.size();
             c.bitmap.assign((1u << lg) / 32, 0);
-            const uint32_t wsh = glop_word_shift(lg);
             for (uint32_t g : keys) {
-                const uint32_t h = glop_qgram_hash(g);
-                uint32_t bits = 1u << glop_bloom_bit1(h, wsh);
-                if (k == 2) bits |= 1u << glop_bloom_bit2(h, wsh);
-                c.bitmap[glop_bloom_word(h, wsh)] |= bits;
+                const uint32_t s1 = glop_slot1(g, lg);
+                c.bitmap[s1 >> 5] |= 1u << (s1 & 31);
+                if (k == 2) {
+                    const uint32_t s2 = glop_slot2(g, lg);
+                    c.bitmap[s2 >> 5] |= 1u << (s2 & 31);
+                }
             }
         } else {
             if (o.stride > 1 || o.qgram || o.bitmap_log2 || o.probe_bits) {
