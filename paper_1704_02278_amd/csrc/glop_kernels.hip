@@ -48,9 +48,28 @@ constexpr uint32_t kStageCap = 16;                // staged matched starts per t
 // over plus 256 from one round plus the word after the tile.
 constexpr uint32_t kRing1 = 2048;
 constexpr uint32_t kRing4 = 512;
+// Stride 4 defers the walks of a workgroup's interior tiles: hit words go to a
+// workgroup-wide LDS list (entry = tile index in the range << 14 | word
+// position 0..8192) and are walked after the whole range has streamed by.
+constexpr uint32_t kHitCap = 8192;
+// Tiles per workgroup at most (per-tile result counters live in LDS).
+constexpr uint32_t kMaxTilesPerWg = 512;
 
 template <int STRIDE>
 constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
+
+// Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
+// per-tile matched-start counts | per-tile record counts.
+template <int STRIDE>
+struct LdsLayout {
+    uint32_t bm_bytes;
+    __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
+    __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
+    __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
+    __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
+    __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + kMaxTilesPerWg * 4; }
+    __host__ __device__ constexpr uint32_t bytes() const { return rec_off() + kMaxTilesPerWg * 8; }
+};
 
 struct ScanParams {
     GlopDevDict d;
@@ -215,10 +234,17 @@ __device__ __forceinline__ uint32_t walk(const ScanParams &P, const uint8_t *cls
     return last;
 }
 
-// Sink of the scan kernel: stage matched starts of the tile, count records.
+// Sink of the scan kernel: stage matched starts of the tile, count records;
+// the tile's totals go to the workgroup's LDS counters.
 struct StageSink {
+    uint32_t *nm_l;    // per-tile matched starts (LDS), indexed by t - tb
+    uint64_t *rec_l;   // per-tile records (LDS)
+    uint64_t tb;
     uint32_t nm = 0;   // matched starts so far (wave-uniform)
     uint64_t rec = 0;  // records so far (wave-uniform)
+
+    __device__ __forceinline__ StageSink(uint32_t *nm_, uint64_t *rec_, uint64_t tb_)
+        : nm_l(nm_), rec_l(rec_), tb(tb_) {}
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, uint64_t /*x0*/, uint32_t off,
                                           uint32_t last) {
@@ -230,10 +256,10 @@ struct StageSink {
         nm += (uint32_t)__popcll(bal);
         rec += wave_sum_u32(m ? P.d.term[2 * last + 1] : 0u);
     }
-    __device__ __forceinline__ void finish(const ScanParams &P, uint64_t t) {
+    __device__ __forceinline__ void finish(const ScanParams &, uint64_t t) {
         if (lane_id() == 0) {
-            P.tile_rec[t] = rec;
-            P.tile_nm[t] = nm;
+            nm_l[t - tb] = nm;
+            rec_l[t - tb] = rec;
         }
     }
 };
@@ -483,55 +509,132 @@ __device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, 
         reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
 }
 
+// Record tile t's hit words in the workgroup list; false if the list is full
+// (then the tile must be walked right away).
+__device__ __forceinline__ bool list_hits(uint64_t t_rel, uint32_t pbits, uint32_t extra_bit, uint32_t *hits,
+                                          uint32_t *hl_count, uint32_t *hl_limit) {
+    const uint32_t lane = lane_id();
+    uint32_t tot;
+    const uint32_t pre = wave_prefix_small<6>((uint32_t)__popc(pbits), tot);
+    const uint32_t n = tot + extra_bit;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(hl_count, n);
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (base + n > kHitCap) {
+        if (lane == 0) atomicMin(hl_limit, base);
+        return false;
+    }
+    const uint32_t tag = (uint32_t)t_rel << 14;
+    uint32_t pos = base + pre, b = pbits;
+    while (b) {
+        const uint32_t i = (uint32_t)__builtin_ctz(b);
+        b &= b - 1u;
+        hits[pos++] = tag | ((i >> 2) * kRoundBytes + lane * 16u + 4u * (i & 3u));
+    }
+    if (extra_bit && lane == 0) hits[base + tot] = tag | (uint32_t)kTileBytes;
+    return true;
+}
+
 template <int STRIDE, bool FILTER, int K, bool Q4>
 __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t hl_count, hl_limit;
     __shared__ uint64_t wsum[kWaves];
+    constexpr bool kDefer = STRIDE == 4;
+    const LdsLayout<STRIDE> L{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
-    uint8_t *cls = lds + P.bm_bytes;
+    uint8_t *cls = lds + L.cls_off();
     const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    uint16_t *queue = reinterpret_cast<uint16_t *>(cls + 256) + wave * ring_cap<STRIDE>();
+    uint16_t *queue = reinterpret_cast<uint16_t *>(lds + L.ring_off()) + wave * ring_cap<STRIDE>();
+    uint32_t *hits = reinterpret_cast<uint32_t *>(lds + L.hits_off());
+    uint32_t *nm_l = reinterpret_cast<uint32_t *>(lds + L.nm_off());
+    uint64_t *rec_l = reinterpret_cast<uint64_t *>(lds + L.rec_off());
 
     // Counts are accumulated by the emit kernel, which runs after this one.
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < P.d.num_patterns;
          k += (uint64_t)gridDim.x * kBlock)
         P.counts[k] = 0;
     stage_tables<FILTER>(P, bm, cls);
+    for (uint32_t k = threadIdx.x; k < kMaxTilesPerWg; k += kBlock) {
+        nm_l[k] = 0;
+        rec_l[k] = 0;
+    }
+    if (threadIdx.x == 0) {
+        hl_count = 0;
+        hl_limit = kHitCap;
+    }
     __syncthreads();
 
     const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
     const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
-    uint64_t total = 0;
     // Interior tiles, pipelined: once a tile's filter bits are known its bytes
-    // are dead, so the next tile's loads go out before this tile's walks.
+    // are dead, so the next tile's loads go out before anything else.
     const uint64_t ib = max(tb, P.int_begin), ie = min(te, P.int_end);
     TileRegs r;
     uint64_t t = ib + wave;
     if (t < ie) load_tile_interior<FILTER>(P, t, r);
     for (; t < ie; t += kWaves) {
-        StageSink sink;
         if constexpr (STRIDE == 4) {
             uint32_t pbits, xb;
             tile_hits4<K, Q4>(P, r, bm, pbits, xb);
             if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
+            if (__ballot(pbits != 0) == 0 && !xb) continue;  // no candidate: counters stay 0
+            if (list_hits(t - tb, pbits, xb, hits, &hl_count, &hl_limit)) continue;
+            StageSink sink(nm_l, rec_l, tb);
             walk_hits4(P, t, pbits, xb, cls, queue, sink);
         } else {
             uint32_t m[kRounds / 2];
             tile_masks1<FILTER, K, Q4>(P, t, r, bm, m);
             if (t + kWaves < ie) load_tile_interior<FILTER>(P, t + kWaves, r);
+            StageSink sink(nm_l, rec_l, tb);
             walk_offsets1(P, t, m, cls, queue, sink);
         }
-        total += sink.rec;
     }
     // Edge tiles (the first and last of the text): bounds-checked loads.
     for (uint64_t e = tb + wave; e < te; e += kWaves) {
         if (e >= ib && e < ie) continue;
         load_tile<FILTER>(P, e, r);
-        StageSink sink;
+        StageSink sink(nm_l, rec_l, tb);
         scan_loaded_tile<STRIDE, FILTER, K, Q4>(P, e, r, bm, cls, queue, sink);
-        total += sink.rec;
     }
-    if (lane == 0) wsum[wave] = total;
+
+    if (kDefer) {
+        // Deferred walks: all waves take 16 listed hit words at a time, four
+        // offsets each.  Matched starts claim staging slots with LDS atomics,
+        // so a tile's slots are in no particular order (the emit kernel sorts
+        // them).
+        __syncthreads();
+        const uint32_t nlist = min(hl_count, hl_limit);
+        for (uint32_t b0 = wave * 16u; b0 < nlist; b0 += kWaves * 16u) {
+            const uint32_t idx = b0 + (lane >> 2);
+            bool act = idx < nlist;
+            const uint32_t ent = act ? hits[idx] : 0u;
+            const uint32_t t_rel = ent >> 14;
+            const int32_t off = (int32_t)(ent & 0x3FFFu) - 3 + (int32_t)(lane & 3);
+            const uint64_t tt = tb + t_rel;
+            const uint64_t x = tt * (uint64_t)kTileBytes + (int64_t)off;
+            act = act && off >= 0 && off < kTileBytes && x >= P.head && x < P.valid_end;
+            const uint32_t last = act ? walk(P, cls, x - P.head) : 0u;
+            if (last) {
+                const uint32_t slot = atomicAdd(&nm_l[t_rel], 1u);
+                if (slot < kStageCap) P.staging[tt * kStageCap + slot] = ((uint64_t)off << 32) | last;
+                atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]),
+                          (unsigned long long)P.d.term[2 * last + 1]);
+            }
+        }
+    }
+    __syncthreads();
+    // The range's tile results, coalesced, and the workgroup total.
+    uint64_t part = 0;
+    for (uint64_t k = tb + threadIdx.x; k < te; k += kBlock) {
+        const uint64_t rc = rec_l[k - tb];
+        P.tile_rec[k] = rc;
+        P.tile_nm[k] = nm_l[k - tb];
+        part += rc;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) wsum[wave] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t s = 0;
@@ -577,10 +680,11 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     __shared__ uint32_t n_over, any_over;
     __shared__ uint64_t over_tile[kBlock];
     __shared__ uint64_t over_base[kBlock];
+    const LdsLayout<STRIDE> L{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
-    uint8_t *cls = lds + P.bm_bytes;
+    uint8_t *cls = lds + L.cls_off();
     const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    uint16_t *queue = reinterpret_cast<uint16_t *>(cls + 256) + wave * ring_cap<STRIDE>();
+    uint16_t *queue = reinterpret_cast<uint16_t *>(lds + L.ring_off()) + wave * ring_cap<STRIDE>();
 
     const uint64_t tb = (uint64_t)blockIdx.x * P.tiles_per_wg;
     const uint64_t te = min(P.ntiles, tb + P.tiles_per_wg);
@@ -615,9 +719,18 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         if (rec > 0) {
             const uint32_t nm = P.tile_nm[t];
             if (nm <= kStageCap) {
+                // Staged starts, in ascending offset (slots may be unordered;
+                // offsets are distinct, so the smallest entry above the last
+                // one written is the next).
                 uint64_t pos = tile_base;
+                uint64_t prev = 0;
                 for (uint32_t e = 0; e < nm; ++e) {
-                    const uint64_t ent = P.staging[t * kStageCap + e];
+                    uint64_t ent = ~0ull;
+                    for (uint32_t j = 0; j < nm; ++j) {
+                        const uint64_t c = P.staging[t * kStageCap + j];
+                        if ((e == 0 || c > prev) && c < ent) ent = c;
+                    }
+                    prev = ent;
                     const uint32_t st = (uint32_t)ent;
                     const uint64_t i = t * (uint64_t)kTileBytes + (ent >> 32) - P.head;
                     const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
@@ -666,6 +779,7 @@ Geometry geometry(uint64_t len, int num_cus) {
     g.ntiles = (len + 15 + kTileBytes - 1) / kTileBytes;
     const uint64_t wgs = (uint64_t)(num_cus > 0 ? num_cus : 1);
     g.tiles_per_wg = g.ntiles ? (g.ntiles + wgs - 1) / wgs : 1;
+    if (g.tiles_per_wg > kMaxTilesPerWg) g.tiles_per_wg = kMaxTilesPerWg;
     g.grid = (uint32_t)(g.ntiles ? (g.ntiles + g.tiles_per_wg - 1) / g.tiles_per_wg : 0);
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.ntiles * 8);
@@ -678,7 +792,7 @@ Geometry geometry(uint64_t len, int num_cus) {
 
 template <int STRIDE>
 constexpr size_t dyn_lds(uint32_t bm_bytes) {
-    return (size_t)bm_bytes + 256 + (size_t)kWaves * ring_cap<STRIDE>() * 2;
+    return LdsLayout<STRIDE>{bm_bytes}.bytes();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4>

@@ -139,3 +139,20 @@ def test_repeated_runs_are_identical():
     for k in range(5):
         say("repeat", k)
         assert_same(gpu_match(d, t), first, f"repeat {k}")
+
+
+def test_dense_hits_at_stride4_fill_the_workgroup_list():
+    # A period-7 text that every 4-byte word of the pattern hits: over 1,000
+    # hit words per 8 KiB tile, so each workgroup's deferred hit list fills
+    # (later tiles walk at once) and tiles exceed their staging slots (the
+    # emit kernel rescans them).  24 MiB gives each workgroup > 8 tiles.
+    pats = [b"abcdefg", b"cdefgab", b"zzzzzzzz"]
+    text = (b"abcdefg" * ((24 << 20) // 7 + 1))[: 24 << 20]
+    want = oracle_match(text, pats)
+    assert want[3] > 3_000_000
+    t = to_device(text, shift=1)
+    for opts in (dict(), dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=1)):
+        say("dense-stride4", opts)
+        d = glop.Dict(pats, **opts)
+        assert d.info()["stride"] == 4
+        assert_same(gpu_match(d, t), want, f"dense stride4 {opts}")
