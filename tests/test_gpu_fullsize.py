@@ -1,0 +1,60 @@
+"""Full-size workloads through the launch configuration bench.py times (needs an MI355X).
+
+* medium (1 GiB, 1,000 patterns): every record and count compared with the
+  bucketed oracle over the whole text.
+* large (4 GiB, 20,000 patterns): the full oracle would take minutes of host
+  time, so the whole output is checked by properties that hold at any size
+  (every record is a true occurrence, ascending and unique, counts add up,
+  every planted occurrence is reported) and 128 sampled windows are compared
+  record by record with the oracle run on each window plus its halo.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+glop = pytest.importorskip("paper_1704_02278_amd")
+from gpu_util import assert_same, gpu_match, oracle_match, say, to_device  # noqa: E402
+
+
+def test_medium_full_size_bit_exact():
+    pats, text, plants = synth.make_workload("medium")
+    say("fullsize medium", text.size)
+    got = gpu_match(glop.Dict(pats), to_device(text))
+    want = oracle_match(text, pats)
+    assert want[3] >= len(plants)
+    assert_same(got, want, "medium 1 GiB")
+
+
+def _properties(text, pats, plants, off, ids, counts, total):
+    assert off.size == total == int(counts.sum())
+    key = off * np.uint64(1 << 32) + ids
+    assert np.all(key[1:] > key[:-1]), "records not strictly ascending"
+    tb = memoryview(text)
+    assert all(bytes(tb[o:o + len(pats[j])]) == pats[j] for o, j in zip(off.tolist(), ids.tolist()))
+    got = set(zip(off.tolist(), ids.tolist()))
+    assert all((o, j) in got for o, j in plants), "a planted occurrence is missing"
+
+
+def test_large_full_size_properties_and_sampled_windows():
+    pats, text, plants = synth.make_workload("large")
+    say("fullsize large", text.size)
+    off, ids, counts, total = gpu_match(glop.Dict(pats), to_device(text))
+    _properties(text, pats, plants, off, ids, counts, total)
+    maxlen = max(len(p) for p in pats)
+    rng = np.random.default_rng(1704)
+    win = 256 << 10
+    starts = np.sort(rng.integers(0, text.size - win, size=128))
+    starts[0], starts[-1] = 0, text.size - win  # include both ends of the text
+    for s in starts.tolist():
+        lo, hi = s, s + win
+        o_off, o_ids, _, _ = oracle.match(text[lo:min(text.size, hi + maxlen - 1)], pats, bucketed=True)
+        keep = o_off < win
+        w_off = o_off[keep].astype(np.uint64) + np.uint64(lo)
+        w_ids = o_ids[keep].astype(np.uint64)
+        a, b = np.searchsorted(off, lo), np.searchsorted(off, hi)
+        assert np.array_equal(off[a:b], w_off) and np.array_equal(ids[a:b], w_ids), f"window at {lo}"
