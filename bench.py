@@ -67,6 +67,27 @@ class HipEvents:
         self.hip.hipEventDestroy(e)
 
 
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("paper_1704_02278_amd/csrc/glop_kernels.hip", "paper_1704_02278_amd/csrc/glop_layout.hpp"):
+        h.update((ROOT / f).read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per scan launch from the committed rocprofv3 counter runs, or
+    None if they were taken on other kernel sources or another workload."""
+    path = ROOT / "profiles" / f"glop_scan_kernel_{workload}_traffic.json"
+    if not path.exists():
+        return None
+    rec = json.loads(path.read_text())
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def cpu_threads() -> int:
     try:
         n = len(os.sched_getaffinity(0))
@@ -230,7 +251,7 @@ def main() -> int:
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "matches": got_total,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.workload),
                      "kernel": "glop_scan_kernel", "kernel_ms_avg": round(scan_avg, 5),
                      "algorithmic_bytes_per_launch": int(scan_bytes)},
         "dictionary": {k: info[k] for k in ("num_states", "num_classes", "stride", "qgram", "bitmap_log2",
