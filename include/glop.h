@@ -83,6 +83,9 @@ typedef struct glop_dict *glop_handle_t;
  *               resident in LDS).
  *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram (independent
  *               hashes: a Bloom filter with one or two hash functions).
+ *   tile_kib    0 = automatic (8); 8 or 16: bytes of text one wavefront streams
+ *               per tile (16 bytes per lane per round, 8 or 16 rounds).  16 is
+ *               available with the stride-4 filter only.
  */
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1
@@ -93,6 +96,7 @@ typedef struct {
     uint32_t qgram;
     uint32_t bitmap_log2;
     uint32_t probe_bits;
+    uint32_t tile_kib;
 } glop_build_opts;
 
 /*
@@ -188,6 +192,58 @@ int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_mat
                   uint64_t workspace_bytes, void *stream, const glop_events_t *events);
 
 /*
+ * Batches: many independent texts ("chunks", e.g. log files of uneven size)
+ * matched in one enqueue.  Each chunk is its own text: offsets are relative to
+ * its first byte and no occurrence spans two chunks.  Per chunk the result is
+ * exactly what glop_match returns for that chunk alone.
+ */
+typedef struct {
+    const uint8_t *text; /* device pointer to the chunk (any alignment; NULL iff len == 0) */
+    uint64_t len;        /* chunk length in bytes */
+} glop_chunk_t;          /* 16 bytes */
+
+typedef struct {
+    uint64_t offset;     /* byte offset within the chunk */
+    uint32_t pattern_id; /* index of the pattern in the build call's array */
+    uint32_t chunk;      /* index of the chunk in the chunk table */
+} glop_batch_match_t;    /* 16 bytes, same layout as glop_match_t */
+
+/* Device workspace glop_match_batch needs for up to nchunks chunks of at most
+ * max_total_bytes bytes in total. */
+uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t max_total_bytes);
+
+/*
+ * Match every chunk of a batch in one persistent scan launch that takes work
+ * items (runs of 8 or 16 KiB tiles, any mix of chunks) from a device work
+ * queue, then one ordered emit launch.  Everything is enqueued on `stream`
+ * and reads its inputs from device memory only, so a captured hipGraph can be
+ * replayed after the chunk table (and the chunks) change, as long as nchunks
+ * and max_total_bytes still hold.
+ *
+ *   d_chunks         device array of nchunks glop_chunk_t.
+ *   nchunks          1..2^31.
+ *   max_total_bytes  upper bound on the sum of the chunks' lengths (sizes the
+ *                    workspace).  If the chunks exceed it the call does no
+ *                    matching and writes *d_total = UINT64_MAX.
+ *   d_out            device array of max_matches records: the batch's
+ *                    occurrences in chunk order, then (offset, id) order; the
+ *                    first max_matches are written.
+ *   d_chunk_first    device array of nchunks: index in that order of chunk
+ *                    c's first occurrence (where it would be if max_matches
+ *                    were unlimited).
+ *   d_chunk_count    device array of nchunks: occurrences in chunk c.
+ *   d_counts         device array of n: per-pattern counts over the batch
+ *                    (NULL iff n == 0).
+ *   d_total          device pointer to the batch's occurrence count (required).
+ *   d_workspace      256-byte aligned, >= glop_batch_workspace_bytes(...).
+ * Allocates nothing.  Errors: as glop_match_ws.
+ */
+int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks, uint64_t max_total_bytes,
+                     glop_batch_match_t *d_out, uint64_t max_matches, uint64_t *d_chunk_first,
+                     uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                     uint64_t workspace_bytes, void *stream);
+
+/*
  * The failureless-trie walk on the host CPU over the same compiled trie (the
  * CPU counterpart the paper measures in Section 7).  A timing baseline and a
  * check of the trie compiler; glop_match never calls it.
@@ -211,7 +267,7 @@ typedef struct {
     uint64_t table_bytes;    /* transition table size on the device */
     uint64_t outlist_ids;    /* total entries of the per-state output lists */
     int32_t filter;          /* GLOP_FILTER_NONE or GLOP_FILTER_QGRAM as chosen */
-    uint32_t stride, qgram, bitmap_log2, probe_bits;
+    uint32_t stride, qgram, bitmap_log2, probe_bits, tile_kib;
     uint64_t filter_keys;    /* distinct q-grams set in the bitmap */
     uint64_t device_bytes;   /* device memory held by the handle */
     int32_t device;          /* HIP device id, or -1 for a host-only handle */

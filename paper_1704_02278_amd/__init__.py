@@ -23,7 +23,7 @@ _PKG = Path(__file__).resolve().parent
 LIB_PATH = _PKG / "libglop.so"
 
 if not LIB_PATH.exists():
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1704_02278_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1704_02278_amd/build.py`")
 
 GLOP_OK = 0
 GLOP_EINVAL = -1
@@ -44,7 +44,15 @@ class glop_match_t(ctypes.Structure):
 
 class glop_build_opts(ctypes.Structure):
     _fields_ = [("filter", ctypes.c_int32), ("stride", ctypes.c_uint32), ("qgram", ctypes.c_uint32),
-                ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32)]
+                ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32)]
+
+
+class glop_chunk_t(ctypes.Structure):
+    _fields_ = [("text", ctypes.c_void_p), ("len", ctypes.c_uint64)]
+
+
+class glop_batch_match_t(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_uint64), ("pattern_id", ctypes.c_uint32), ("chunk", ctypes.c_uint32)]
 
 
 class glop_events_t(ctypes.Structure):
@@ -57,7 +65,7 @@ class glop_info_t(ctypes.Structure):
         ("num_classes", ctypes.c_uint32), ("num_states", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
         ("outlist_ids", ctypes.c_uint64), ("filter", ctypes.c_int32), ("stride", ctypes.c_uint32),
         ("qgram", ctypes.c_uint32), ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32),
-        ("filter_keys", ctypes.c_uint64),
+        ("tile_kib", ctypes.c_uint32), ("filter_keys", ctypes.c_uint64),
         ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
     ]
 
@@ -77,6 +85,9 @@ _SIGNATURES = {
     "glop_workspace_bytes": (_u64, [_vp, _u64]),
     "glop_match_ws": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _vp,
                                      ctypes.POINTER(glop_events_t)]),
+    "glop_batch_workspace_bytes": (_u64, [_vp, ctypes.c_uint32, _u64]),
+    "glop_match_batch": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64,
+                                        _vp]),
     "glop_cpu_walk": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_int]),
     "glop_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(glop_info_t)]),
     "glop_last_error": (ctypes.c_int, []),
@@ -112,17 +123,17 @@ def _pattern_arrays(patterns):
     return keep, ptrs, lens, len(pats)
 
 
-def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0):
-    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits))
+def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0, tile_kib=0):
+    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits), int(tile_kib))
 
 
 class Dict:
     """A compiled dictionary on the current device (or host-only with ``device=False``)."""
 
     def __init__(self, patterns, *, device: bool = True, filter=GLOP_FILTER_AUTO, stride=0, qgram=0,
-                 bitmap_log2=0, probe_bits=0):
+                 bitmap_log2=0, probe_bits=0, tile_kib=0):
         keep, ptrs, lens, n = _pattern_arrays(patterns)
-        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits)
+        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits, tile_kib)
         fn = glop_build_ex if device else glop_compile
         h = fn(ctypes.cast(ptrs, _u8pp), lens, n, ctypes.byref(opts))
         if not h:
@@ -196,6 +207,65 @@ class Dict:
             got = int(total.item())
         k = min(cap, got)
         return out[:k, 0], out[:k, 1], counts[: self.num_patterns], got
+
+    def batch_workspace_bytes(self, nchunks: int, max_total_bytes: int) -> int:
+        return int(glop_batch_workspace_bytes(self._h, int(nchunks), int(max_total_bytes)))
+
+    def match_batch_into(self, chunk_table, nchunks, max_total_bytes, out, chunk_first, chunk_count, counts, total,
+                         workspace, *, max_matches=None, stream=None):
+        """Enqueue a batch into caller-owned CUDA tensors (no allocation, no sync).
+
+        chunk_table: int64 CUDA tensor [nchunks, 2] of (device pointer, length);
+        out: int64 CUDA tensor [cap, 2] (16-byte records: offset, pattern id |
+        chunk << 32); chunk_first, chunk_count: int64 [nchunks]; counts: int64
+        [n]; total: int64 [1]; workspace: uint8 CUDA tensor, 256-byte aligned.
+        """
+        import torch
+
+        cap = int(out.shape[0]) if max_matches is None else int(max_matches)
+        s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+        _check(glop_match_batch(self._h, chunk_table.data_ptr(), int(nchunks), int(max_total_bytes),
+                                out.data_ptr(), cap, chunk_first.data_ptr(), chunk_count.data_ptr(),
+                                counts.data_ptr(), total.data_ptr(), workspace.data_ptr(), int(workspace.numel()),
+                                s), "glop_match_batch")
+
+    def match_batch(self, chunks, max_matches=None, stream=None):
+        """Match a list of uint8 CUDA tensors as one batch.
+
+        Returns (offsets, ids, chunk_ids, chunk_first, chunk_count, counts,
+        total); the first three are views of the records (chunk order, then
+        offset, then id).  With ``max_matches=None`` the output is sized to
+        fit (this synchronises).
+        """
+        import torch
+
+        dev = chunks[0].device
+        n = len(chunks)
+        table = torch.tensor([[c.data_ptr() if c.numel() else 0, c.numel()] for c in chunks], dtype=torch.int64)
+        table = table.to(dev)
+        total_bytes = sum(int(c.numel()) for c in chunks)
+        first = torch.empty(n, dtype=torch.int64, device=dev)
+        count = torch.empty(n, dtype=torch.int64, device=dev)
+        counts = torch.empty(max(1, self.num_patterns), dtype=torch.int64, device=dev)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        wsb = self.batch_workspace_bytes(n, total_bytes)
+        ws = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:]
+        cap = max(1024, total_bytes // 1024) if max_matches is None else int(max_matches)
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+        self.match_batch_into(table, n, total_bytes, out, first, count, counts, total, ws, max_matches=cap,
+                              stream=stream)
+        got = int(total.item())
+        if max_matches is None and got > cap:
+            cap = got
+            out = torch.empty((cap, 2), dtype=torch.int64, device=dev)
+            self.match_batch_into(table, n, total_bytes, out, first, count, counts, total, ws, max_matches=cap,
+                                  stream=stream)
+            got = int(total.item())
+        k = min(cap, got)
+        rec = out[:k]
+        return (rec[:, 0], rec[:, 1] & 0xFFFFFFFF, rec[:, 1] >> 32, first, count, counts[: self.num_patterns],
+                got)
 
     def cpu_walk(self, text, threads: int = 1, max_matches=None):
         """Failureless-trie walk on the host (baseline); returns numpy arrays like ``match``."""

@@ -1,6 +1,8 @@
 """Build ``libglop.so`` (gfx950) in-tree with hipcc.
 
-    python -m paper_1704_02278_amd.build
+    python paper_1704_02278_amd/build.py
+
+(Run it by path: importing the package would load the library being rebuilt.)
 """
 
 from __future__ import annotations
@@ -8,13 +10,16 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libglop.so"
-SOURCES = ["glop_capi.cpp", "glop_trie.cpp", "glop_kernels.hip"]
+SOURCES = ["glop_capi.cpp", "glop_trie.cpp", "glop_kernels.hip"] + [
+    f"glop_kernels_{tag}.hip" for tag in "abcdef"
+]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are kept out of every device build.
@@ -26,8 +31,7 @@ def build(verbose: bool = False) -> Path:
     """Compile every source and link the shared library (always rebuilds)."""
     objdir = PKG / "_build"
     objdir.mkdir(exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         obj = objdir / (src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC, *DEVICE_FLAGS, *COMMON_FLAGS, *lang, "-c", str(CSRC / src), "-o", str(obj)]
@@ -39,7 +43,11 @@ def build(verbose: bool = False) -> Path:
             raise RuntimeError(f"hipcc failed on {src}:\n{errs}")
         if errs.strip() and verbose:
             print(errs, file=sys.stderr)
-        objs.append(str(obj))
+        return str(obj)
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB.with_name(LIB.name + ".tmp")
     cmd = [HIPCC, *DEVICE_FLAGS, "-shared", "-fPIC", *objs, "-o", str(tmp)]
     res = subprocess.run(cmd, capture_output=True, text=True)

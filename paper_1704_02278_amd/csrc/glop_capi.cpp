@@ -108,6 +108,7 @@ int upload(glop_dict *h) {
     d.stride = c.stride;
     d.bitmap_log2 = c.bitmap_log2;
     d.probe_bits = c.probe_bits;
+    d.tile_kib = c.tile_kib;
     d.filter = c.filter;
     return GLOP_OK;
 }
@@ -237,6 +238,50 @@ int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_
     return ok();
 }
 
+uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t max_total_bytes) {
+    if (!h) {
+        fail(GLOP_EINVAL, "NULL handle");
+        return 0;
+    }
+    ok();
+    return glop::batch_workspace_bytes(nchunks, max_total_bytes);
+}
+
+int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks, uint64_t max_total_bytes,
+                     glop_batch_match_t *d_out, uint64_t max_matches, uint64_t *d_chunk_first,
+                     uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                     uint64_t workspace_bytes, void *stream) {
+    if (!h) return fail(GLOP_EINVAL, "NULL handle");
+    if (nchunks == 0 || nchunks > (1u << 31)) return fail(GLOP_EINVAL, "nchunks must be 1..2^31");
+    if (!d_chunks || !d_chunk_first || !d_chunk_count || !d_total)
+        return fail(GLOP_EINVAL, "NULL chunk table, per-chunk output or total");
+    if (max_matches > 0 && !d_out) return fail(GLOP_EINVAL, "NULL output with max_matches > 0");
+    if (h->c.num_patterns > 0 && !d_counts) return fail(GLOP_EINVAL, "NULL counts with a non-empty dictionary");
+    if (max_total_bytes > (1ull << 62)) return fail(GLOP_EINVAL, "max_total_bytes too large");
+    int rc = check_device(h);
+    if (rc != GLOP_OK) return rc;
+    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes);
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
+        return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
+                                     " bytes");
+    glop::BatchLaunch a{};
+    a.d = h->dd;
+    a.chunks = d_chunks;
+    a.nchunks = nchunks;
+    a.max_total_bytes = max_total_bytes;
+    a.out = d_out;
+    a.max_matches = max_matches;
+    a.chunk_first = d_chunk_first;
+    a.chunk_count = d_chunk_count;
+    a.counts = d_counts;
+    a.total = d_total;
+    a.workspace = d_workspace;
+    a.num_cus = h->num_cus;
+    hipError_t e = glop::launch_batch(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return ok();
+}
+
 int glop_cpu_walk(glop_handle_t h, const uint8_t *text, uint64_t len, glop_match_t *out,
                   uint64_t max_matches, uint64_t *counts, uint64_t *total, int threads) {
     if (!h) return fail(GLOP_EINVAL, "NULL handle");
@@ -261,6 +306,7 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->qgram = c.qgram;
     out->bitmap_log2 = c.bitmap_log2;
     out->probe_bits = c.probe_bits;
+    out->tile_kib = c.tile_kib;
     out->filter_keys = c.filter_keys;
     out->device_bytes = h->blob_bytes;
     out->device = h->blob ? h->device : -1;

@@ -22,8 +22,29 @@ struct MatchLaunch {
     const glop_events_t *events;  // may be null
 };
 
+struct BatchLaunch {
+    GlopDevDict d;
+    const glop_chunk_t *chunks;
+    uint32_t nchunks;
+    uint64_t max_total_bytes;
+    glop_batch_match_t *out;
+    uint64_t max_matches;
+    uint64_t *chunk_first;
+    uint64_t *chunk_count;
+    uint64_t *counts;
+    uint64_t *total;
+    void *workspace;
+    int num_cus;
+};
+
 // Device workspace needed for a text of `len` bytes (any alignment).
 uint64_t workspace_bytes(uint64_t len, int num_cus);
+
+// Device workspace needed for a batch of nchunks chunks, max_total_bytes in all.
+uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes);
+
+// Enqueue a batch on `stream`.
+hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream);
 
 // Enqueue the whole match on `stream`.
 hipError_t launch_match(const MatchLaunch &a, hipStream_t stream);

@@ -1,0 +1,1118 @@
+// Matching kernels: shared device code and the Kernels<> launch template.
+// Each variant translation unit instantiates a disjoint set of Kernels<>;
+// glop_kernels.hip holds the dispatch.
+#pragma once
+// Matching kernels for gfx950 (CDNA4, wave64).
+//
+// Every byte offset of the text starts a walk of the failureless trie
+// (Section 5).  The work is split in two kernels:
+//
+// scan  -- streams the text once from HBM.  Each wave owns 8 KiB tiles; a lane
+//          holds 16 consecutive bytes per 1 KiB round (one coalesced 16-byte
+//          load).  With the q-gram filter, the lane first probes an LDS Bloom
+//          filter that summarises the trie's first q levels: an offset whose
+//          q-gram misses the filter cannot start any pattern and needs no walk.
+//          At stride 4 only aligned 4-byte words are probed; a word that hits
+//          stands for the four offsets whose patterns must contain it.  This is
+//          the prefix-filter stage of Sections 2 and 5, made exact because
+//          every surviving offset is then walked through the full trie.
+//          Survivors are appended in order to a per-wave LDS ring and walked
+//          64 at a time, one per lane, so walks run with full waves instead of
+//          the few divergent lanes Section 5 describes.  A tile's next loads
+//          are issued as soon as its filter bits are known, before its walks.  A walk reads bytes
+//          past its tile as needed (the overlap of at least the longest
+//          pattern minus one byte that Section 4 requires between chunks).
+//          Each tile's matched starts (offset, deepest terminal state) are
+//          staged in workspace; the tile's record count is written out.
+//          At stride 4 the walks are deferred: hit words go to a
+//          workgroup-wide LDS list, and waves take 16 listed words (64
+//          offsets) at a time between their tiles, so no wave stalls on walk
+//          latency for a single tile and the stream never pauses.
+// emit  -- turns the per-tile record counts into output positions (sum over
+//          earlier work items, then a block scan over the tiles) and writes the
+//          (offset, id) records in order, plus the per-pattern counts.  A tile
+//          with more matched starts than the staging slots is rescanned here
+//          and written directly.
+//
+// One text is split statically: workgroup g owns work item g (a run of up to
+// 512 tiles).  A batch of chunks is first laid out as one list of tiles (each
+// chunk starts a new tile; a prep kernel scans the chunk table and maps every
+// tile to its chunk), and the scan workgroups stay resident and take work
+// items from a device ticket until none is left.
+//
+// No workgroup ever waits for another, so the kernels are safe to run beside
+// any other work on the device.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "glop_kernels.hpp"
+
+namespace glop {
+namespace detail {
+
+constexpr int kWave = 64;
+constexpr int kWaves = 16;                  // waves per workgroup
+constexpr int kBlock = kWave * kWaves;      // 1024 threads
+constexpr int kRoundBytes = kWave * 16;     // 1 KiB: 16 bytes per lane
+constexpr uint32_t kMinTileBytes = 8 * kRoundBytes;
+constexpr uint32_t kStageCap = 16;          // staged matched starts per tile
+// Per-wave LDS rings (u16 entries).  Stride 1 queues offsets: at most 63 left
+// over plus 1024 from one round.  Stride 4 queues hit words: at most 15 left
+// over plus 256 from one round plus the word after the tile.
+constexpr uint32_t kRing1 = 2048;
+constexpr uint32_t kRing4 = 512;
+// Deferred hit list (stride 4): entry = tile index in the item << 15 | word
+// position in the tile (0 .. tile bytes); unwritten slots hold kHitFree.
+constexpr uint32_t kHitCap = 8192;
+constexpr uint32_t kHitFree = 0xFFFFFFFFu;
+constexpr uint32_t kPosBits = 15;
+// Tiles per work item at most (per-tile result counters live in LDS).
+constexpr uint32_t kMaxTilesPerItem = 512;
+
+// Batch metadata words in the workspace.
+enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaWords = 8 };
+
+template <int STRIDE>
+constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
+
+// Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
+// per-tile matched-start counts | per-tile record counts.
+template <int STRIDE>
+struct LdsLayout {
+    uint32_t bm_bytes;
+    __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
+    __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
+    __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
+    __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
+    __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + kMaxTilesPerItem * 4; }
+    __host__ __device__ constexpr uint32_t bytes() const { return rec_off() + kMaxTilesPerItem * 8; }
+};
+
+// A text as the kernels see it: coordinates x count bytes from abase, the
+// text's first byte rounded down to 16 bytes.
+struct Span {
+    const uint8_t *abase;
+    uint64_t head;       // coordinate of the first text byte (0..15)
+    uint64_t span_end;   // head + len
+    uint64_t valid_end;  // starts x with head <= x < valid_end leave room for the shortest pattern
+};
+
+__host__ __device__ __forceinline__ Span make_span(const uint8_t *text, uint64_t len, uint32_t min_len) {
+    Span s;
+    s.head = reinterpret_cast<uintptr_t>(text) & 15u;
+    s.abase = text - s.head;
+    s.span_end = s.head + len;
+    s.valid_end = len >= min_len ? s.head + len - min_len + 1 : 0;
+    return s;
+}
+
+struct ScanParams {
+    GlopDevDict d;
+    Span one;                    // single text
+    uint64_t ntiles;             // single text: tiles
+    const glop_chunk_t *chunks;  // batch: chunk table
+    uint32_t nchunks;
+    uint64_t *tile_start;        // batch: first tile of each chunk, nchunks + 1
+    uint32_t *tile_chunk;        // batch: chunk of each tile
+    uint64_t *meta;              // batch: kMeta* words
+    uint64_t tile_cap;           // batch: tiles the workspace holds
+    uint64_t tiles_per_item;
+    uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
+    uint64_t *tile_rec;          // records per tile
+    uint32_t *tile_nm;           // matched starts per tile
+    uint64_t *staging;           // kStageCap per tile: (offset in tile << 32) | state
+    uint64_t *itemsum;           // records per work item
+    uint64_t *counts;            // per-pattern counts
+};
+
+struct EmitParams {
+    glop_match_t *out;     // (offset, id, chunk) records; glop_batch_match_t has this layout
+    uint64_t max_matches;
+    uint64_t *total;       // single text (may be null)
+    uint64_t *chunk_first; // batch
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive scan over the wave; `total` = sum.
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t &total) {
+    const uint32_t lane = lane_id();
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o);
+        if (lane >= (uint32_t)o) incl += y;
+    }
+    total = __shfl(incl, kWave - 1);
+    return incl - v;
+}
+
+// Exclusive prefix over the wave of small counts c < 2^BITS, and the total.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t &total) {
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const uint64_t bal = __ballot((c >> b) & 1u);
+        pre += (uint32_t)__popcll(bal & lanemask_lt()) << b;
+        tot += (uint32_t)__popcll(bal) << b;
+    }
+    total = tot;
+    return pre;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive scan over the block (1024 threads); `total` = block sum.
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh, uint64_t &total) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint64_t y = __shfl_up(incl, o);
+        if (lane >= (uint32_t)o) incl += y;
+    }
+    if (lane == kWave - 1) sh[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        const uint64_t w = lane < kWaves ? sh[lane] : 0ull;
+        uint64_t wi = w;
+#pragma unroll
+        for (int o = 1; o < kWaves; o <<= 1) {
+            uint64_t y = __shfl_up(wi, o);
+            if (lane >= (uint32_t)o) wi += y;
+        }
+        if (lane < kWaves) sh[lane] = wi - w;
+        if (lane == kWaves - 1) sh[kWaves] = wi;
+    }
+    __syncthreads();
+    const uint64_t excl = sh[wave] + incl - v;
+    total = sh[kWaves];
+    __syncthreads();
+    return excl;
+}
+
+// Sum over the block (1024 threads), returned to every thread.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    uint64_t s = 0;
+    for (int w = 0; w < kWaves; ++w) s += sh[w];
+    __syncthreads();
+    return s;
+}
+
+// 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
+__device__ __forceinline__ uint4 load16(const Span &s, uint64_t x) {
+    if (x >= s.head && x + 16 <= s.span_end) return *reinterpret_cast<const uint4 *>(s.abase + x);
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint64_t y = x + k;
+        const uint32_t b = (y >= s.head && y < s.span_end) ? (uint32_t)s.abase[y] : 0u;
+        const uint32_t sh = 8 * (k & 3);
+        if (k < 4) w0 |= b << sh;
+        else if (k < 8) w1 |= b << sh;
+        else if (k < 12) w2 |= b << sh;
+        else w3 |= b << sh;
+    }
+    return make_uint4(w0, w1, w2, w3);
+}
+
+// 4 text bytes at aligned coordinate x (multiple of 4); outside reads as 0.
+__device__ __forceinline__ uint32_t load4(const Span &s, uint64_t x) {
+    if (x >= s.head && x + 4 <= s.span_end) return *reinterpret_cast<const uint32_t *>(s.abase + x);
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t y = x + k;
+        w |= ((y >= s.head && y < s.span_end) ? (uint32_t)s.abase[y] : 0u) << (8 * k);
+    }
+    return w;
+}
+
+// Bloom probe: 1 if every probe bit of q-gram g is set.
+template <int K, bool Q4>
+__device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t sh) {
+    if (!Q4) g &= qmask;
+    const uint32_t s1 = glop_hash1(g) >> sh;
+    uint32_t hit = bm[s1 >> 5] >> (s1 & 31);
+    if (K == 2) {
+        const uint32_t s2 = glop_hash2(g) >> sh;
+        hit &= bm[s2 >> 5] >> (s2 & 31);
+    }
+    return hit & 1u;
+}
+
+// Offsets x .. x+15 that may start a pattern: head <= x+u < valid_end.
+__device__ __forceinline__ uint32_t valid_mask16(const Span &s, uint64_t x) {
+    int64_t lo = (int64_t)s.head - (int64_t)x;
+    int64_t hi = (int64_t)s.valid_end - (int64_t)x;
+    lo = lo < 0 ? 0 : (lo > 16 ? 16 : lo);
+    hi = hi < 0 ? 0 : (hi > 16 ? 16 : hi);
+    if (hi <= lo) return 0u;
+    return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// The failureless walk from coordinate x (Section 5): follow goto edges while
+// they exist; return the deepest terminal state passed (0 = none).  Text bytes
+// come 8 at a time from aligned loads; the walk may run past its tile up to
+// the end of its text.
+__device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, const uint8_t *cls, uint64_t x) {
+    const uint32_t C = d.num_classes;
+    uint32_t st = 0, last = 0;
+    uint64_t win = 0;
+    uint32_t have = 0;
+    while (x < s.span_end) {
+        if (have == 0) {
+            const uint64_t xa = x & ~7ull;
+            if (xa >= s.head && xa + 8 <= s.span_end) {
+                win = *reinterpret_cast<const uint64_t *>(s.abase + xa);
+            } else {
+                win = 0;
+                for (int k = 0; k < 8; ++k) {
+                    const uint64_t y = xa + k;
+                    if (y >= s.head && y < s.span_end) win |= (uint64_t)s.abase[y] << (8 * k);
+                }
+            }
+            win >>= 8 * (x - xa);
+            have = 8 - (uint32_t)(x - xa);
+        }
+        const uint32_t c = cls[win & 0xFFu];
+        win >>= 8;
+        --have;
+        const uint32_t e = d.delta[(uint64_t)st * C + c];
+        if (e == 0) break;
+        st = e & GLOP_STATE_MASK;
+        if (e & GLOP_TERM_BIT) last = st;
+        ++x;
+    }
+    return last;
+}
+
+// Where tile t lies: its text (or chunk), its first coordinate, and whether
+// every byte it loads is inside that text.
+struct TileInfo {
+    Span s;
+    uint64_t x0;
+    uint32_t chunk;
+    bool interior;
+};
+
+template <bool BATCH, int TILE>
+__device__ __forceinline__ TileInfo tile_info(const ScanParams &P, uint64_t t) {
+    TileInfo ti;
+    uint64_t k = t;
+    if (BATCH) {
+        ti.chunk = P.tile_chunk[t];
+        k = t - P.tile_start[ti.chunk];
+        const glop_chunk_t ch = P.chunks[ti.chunk];
+        ti.s = make_span(ch.text, ch.len, P.d.min_len);
+    } else {
+        ti.chunk = 0;
+        ti.s = P.one;
+    }
+    ti.x0 = k * (uint64_t)TILE;
+    ti.interior = ti.x0 >= ti.s.head && ti.x0 + TILE + 4 <= ti.s.span_end;
+    return ti;
+}
+
+// A wave's tile in registers: 16 bytes per lane per round, plus the first
+// word after the tile (for the probes of the tile's last offsets).
+template <int R>
+struct TileRegs {
+    uint4 v[R];
+    uint32_t extra;
+};
+
+template <int R, bool FILTER>
+__device__ __forceinline__ void load_tile(const TileInfo &ti, TileRegs<R> &r) {
+    const uint64_t x = ti.x0 + lane_id() * 16u;
+    if (ti.interior) {
+        const uint8_t *p = ti.s.abase + x;
+#pragma unroll
+        for (int k = 0; k < R; ++k) r.v[k] = *reinterpret_cast<const uint4 *>(p + k * kRoundBytes);
+        r.extra = FILTER ? *reinterpret_cast<const uint32_t *>(ti.s.abase + ti.x0 + R * kRoundBytes) : 0u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) r.v[k] = load16(ti.s, x + (uint64_t)k * kRoundBytes);
+        r.extra = FILTER ? load4(ti.s, ti.x0 + R * kRoundBytes) : 0u;
+    }
+}
+
+// Sink of the scan kernel: stage matched starts of the tile, count records;
+// the tile's totals go to the item's LDS counters.
+struct StageSink {
+    uint32_t *nm_l;    // per-tile matched starts (LDS), indexed by t - tb
+    uint64_t *rec_l;   // per-tile records (LDS)
+    uint64_t tb;
+    uint32_t nm = 0;   // matched starts so far (wave-uniform)
+    uint64_t rec = 0;  // records so far (wave-uniform)
+
+    __device__ __forceinline__ StageSink(uint32_t *nm_, uint64_t *rec_, uint64_t tb_)
+        : nm_l(nm_), rec_l(rec_), tb(tb_) {}
+
+    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, const TileInfo &, uint32_t off,
+                                          uint32_t last) {
+        const bool m = last != 0;
+        const uint64_t bal = __ballot(m);
+        if (bal == 0) return;
+        const uint32_t pos = nm + (uint32_t)__popcll(bal & lanemask_lt());
+        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = ((uint64_t)off << 32) | last;
+        nm += (uint32_t)__popcll(bal);
+        rec += wave_sum_u32(m ? P.d.term[2 * last + 1] : 0u);
+    }
+    __device__ __forceinline__ void finish(uint64_t t) {
+        if (lane_id() == 0) {
+            nm_l[t - tb] = nm;
+            rec_l[t - tb] = rec;
+        }
+    }
+};
+
+// Sink of the emit kernel's rescan: write the records directly, in order.
+struct DirectSink {
+    const EmitParams *E;
+    uint64_t base;        // output position of the tile's first record
+    uint64_t cursor = 0;  // records written so far in the tile
+
+    __device__ __forceinline__ DirectSink(const EmitParams *e, uint64_t b) : E(e), base(b) {}
+
+    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
+                                          uint32_t last) {
+        const bool m = last != 0;
+        if (__ballot(m) == 0) return;
+        const uint32_t first = m ? P.d.term[2 * last] : 0u;
+        const uint32_t cnt = m ? P.d.term[2 * last + 1] : 0u;
+        uint32_t tot;
+        const uint32_t excl = wave_excl_scan_u32(cnt, tot);
+        if (m) {
+            const uint64_t i = ti.x0 + off - ti.s.head;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t id = P.d.outids[first + k];
+                const uint64_t pos = base + cursor + excl + k;
+                if (pos < E->max_matches) E->out[pos] = glop_match_t{i, id, ti.chunk};
+                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+            }
+        }
+        cursor += tot;
+    }
+    __device__ __forceinline__ void finish(uint64_t) {}
+};
+
+// ---- stride 4: one probe per aligned word ---------------------------------
+//
+// Offset x needs the word at roundup4(x) to hit (every pattern is at least
+// q + 3 bytes, so that word lies inside any occurrence starting at x, at
+// pattern position t = roundup4(x) - x in 0..3).  Bit 4k+w of the lane's
+// result is the word at x0 + k*1024 + lane*16 + 4w; `extra` is the word after
+// the tile (it serves the tile's last three offsets).
+template <int R>
+using HitBits = typename std::conditional<(4 * R > 32), uint64_t, uint32_t>::type;
+
+template <int R, int K, bool Q4>
+__device__ __forceinline__ void tile_hits4(const GlopDevDict &d, const TileRegs<R> &r, const uint32_t *bm,
+                                           HitBits<R> &pbits, uint32_t &extra_bit) {
+    const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
+    HitBits<R> b = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        b |= (HitBits<R>)probe<K, Q4>(bm, r.v[k].x, qmask, sh) << (4 * k);
+        b |= (HitBits<R>)probe<K, Q4>(bm, r.v[k].y, qmask, sh) << (4 * k + 1);
+        b |= (HitBits<R>)probe<K, Q4>(bm, r.v[k].z, qmask, sh) << (4 * k + 2);
+        b |= (HitBits<R>)probe<K, Q4>(bm, r.v[k].w, qmask, sh) << (4 * k + 3);
+        // Finish each round's probes in place: left alone, the compiler defers
+        // the bit tests and spills every hash and word.
+        __asm__ volatile("" : "+v"(b));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    pbits = b;
+    extra_bit = probe<K, Q4>(bm, r.extra, qmask, sh);
+}
+
+template <class B>
+__device__ __forceinline__ uint32_t popcount(B b) {
+    return sizeof(B) == 8 ? (uint32_t)__popcll((uint64_t)b) : (uint32_t)__popc((uint32_t)b);
+}
+
+// Walk the four offsets of each of n queued hit words: lanes 4h..4h+3 take hit
+// h's offsets p-3, p-2, p-1, p, so a batch of 16 hits is in offset order.
+template <int TILE, class Sink>
+__device__ __forceinline__ void walk_hit_batch(const ScanParams &P, uint64_t t, const TileInfo &ti,
+                                               const uint8_t *cls, const uint16_t *queue, uint32_t qhead,
+                                               uint32_t n, Sink &sink) {
+    const uint32_t lane = lane_id();
+    const uint32_t h = lane >> 2;
+    bool act = h < n;
+    const int32_t p = act ? (int32_t)queue[(qhead + h) & (kRing4 - 1)] : 0;
+    const int32_t off = p - 3 + (int32_t)(lane & 3);
+    const uint64_t x = ti.x0 + (int64_t)off;
+    act = act && off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end;
+    const uint32_t last = act ? walk(P.d, ti.s, cls, x) : 0u;
+    sink.batch(P, t, ti, act ? (uint32_t)off : 0u, last);
+}
+
+// Walk a tile's hit words right away (per-wave ring).
+template <int R, class Sink>
+__device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, const TileInfo &ti, HitBits<R> pbits,
+                                           uint32_t extra_bit, const uint8_t *cls, uint16_t *queue, Sink &sink) {
+    constexpr int TILE = R * kRoundBytes;
+    const uint32_t lane = lane_id();
+    if (__ballot(pbits != 0) != 0 || extra_bit) {
+        uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            uint32_t bits = (uint32_t)(pbits >> (4 * k)) & 0xFu;
+            if (__ballot(bits != 0) == 0) continue;
+            uint32_t tot;
+            uint32_t pos = qtail + wave_prefix_small<3>((uint32_t)__popc(bits), tot);
+            const uint32_t base = (uint32_t)k * kRoundBytes + lane * 16u;
+            while (bits) {
+                const uint32_t w = (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1u;
+                queue[(pos++) & (kRing4 - 1)] = (uint16_t)(base + 4u * w);
+            }
+            qtail += tot;
+            wave_lds_sync();
+            for (; qtail - qhead >= 16u; qhead += 16u) walk_hit_batch<TILE>(P, t, ti, cls, queue, qhead, 16u, sink);
+        }
+        if (extra_bit) {
+            if (lane == 0) queue[qtail & (kRing4 - 1)] = (uint16_t)TILE;
+            qtail += 1;
+            wave_lds_sync();
+        }
+        for (; qtail != qhead;) {
+            const uint32_t n = min(16u, qtail - qhead);
+            walk_hit_batch<TILE>(P, t, ti, cls, queue, qhead, n, sink);
+            qhead += n;
+        }
+    }
+    sink.finish(t);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Workgroup hit list of the current work item (stride 4).
+struct HitList {
+    uint32_t *hits;     // kHitCap entries (LDS)
+    uint32_t *count;    // entries reserved, all of which get written (LDS)
+    uint32_t *claimed;  // entries taken by walkers (LDS)
+};
+
+// Record tile t's hit words in the list; false if they do not fit (then the
+// tile must be walked right away).  Space is reserved with compare-and-swap so
+// `count` never exceeds what will be written.
+template <int R>
+__device__ __forceinline__ bool list_hits(const HitList &L, uint32_t t_rel, HitBits<R> pbits, uint32_t extra_bit) {
+    const uint32_t lane = lane_id();
+    uint32_t tot;
+    const uint32_t pre = wave_prefix_small<7>(popcount(pbits), tot);
+    const uint32_t n = tot + extra_bit;
+    uint32_t base = 0, ok = 0;
+    if (lane == 0) {
+        uint32_t c = __hip_atomic_load(L.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        while (c + n <= kHitCap) {
+            const uint32_t prev = atomicCAS(L.count, c, c + n);
+            if (prev == c) {
+                base = c;
+                ok = 1;
+                break;
+            }
+            c = prev;
+        }
+    }
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (!ok) return false;
+    const uint32_t tag = t_rel << kPosBits;
+    uint32_t pos = base + pre;
+    HitBits<R> b = pbits;
+    while (b) {
+        const uint32_t i = (uint32_t)(sizeof(b) == 8 ? __builtin_ctzll((uint64_t)b) : __builtin_ctz((uint32_t)b));
+        b &= b - 1;
+        __hip_atomic_store(&L.hits[pos++], tag | ((i >> 2) * kRoundBytes + lane * 16u + 4u * (i & 3u)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (extra_bit && lane == 0)
+        __hip_atomic_store(&L.hits[base + tot], tag | (uint32_t)(R * kRoundBytes), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    return true;
+}
+
+// Walk n listed hit words from index `first` (n <= 16).  Matched starts claim
+// their tile's staging slots with LDS atomics, so a tile's slots are in no
+// particular order (the emit kernel sorts them).
+template <bool BATCH, int TILE>
+__device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &L, uint32_t first, uint32_t n,
+                                            uint64_t tb, const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l) {
+    const uint32_t lane = lane_id();
+    const uint32_t h = lane >> 2;
+    bool act = h < n;
+    uint32_t ent = 0;
+    if (act) {
+        // Every reserved entry is written right after its reservation.
+        while ((ent = __hip_atomic_load(&L.hits[first + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) ==
+               kHitFree)
+            __builtin_amdgcn_s_sleep(1);
+    }
+    const uint32_t t_rel = ent >> kPosBits;
+    const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
+    const uint64_t t = tb + t_rel;
+    uint32_t last = 0;
+    if (act) {
+        const TileInfo ti = tile_info<BATCH, TILE>(P, t);
+        const uint64_t x = ti.x0 + (int64_t)off;
+        if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) last = walk(P.d, ti.s, cls, x);
+    }
+    if (last) {
+        const uint32_t slot = atomicAdd(&nm_l[t_rel], 1u);
+        if (slot < kStageCap) P.staging[t * kStageCap + slot] = ((uint64_t)off << 32) | last;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)P.d.term[2 * last + 1]);
+    }
+}
+
+// Take 16 listed hit words if that many are waiting, and walk them.
+template <bool BATCH, int TILE>
+__device__ __forceinline__ void claim_and_walk(const ScanParams &P, const HitList &L, uint64_t tb,
+                                               const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l) {
+    uint32_t got = 0, first = 0;
+    if (lane_id() == 0) {
+        uint32_t c = __hip_atomic_load(L.claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        while (c + 16u <= __hip_atomic_load(L.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            const uint32_t prev = atomicCAS(L.claimed, c, c + 16u);
+            if (prev == c) {
+                got = 1;
+                first = c;
+                break;
+            }
+            c = prev;
+        }
+    }
+    got = __builtin_amdgcn_readfirstlane(got);
+    first = __builtin_amdgcn_readfirstlane(first);
+    if (got) walk_listed<BATCH, TILE>(P, L, first, 16u, tb, cls, nm_l, rec_l);
+}
+
+// ---- stride 1: one probe per offset (or none: walk every offset) ----------
+//
+// Bit u of round k's 16-bit mask (word k/2, half k%2) marks offset
+// x0 + k*1024 + lane*16 + u as not ruled out.
+template <int R, bool FILTER, int K, bool Q4>
+__device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo &ti, const TileRegs<R> &r,
+                                            const uint32_t *bm, uint32_t (&m)[R / 2]) {
+    const uint32_t lane = lane_id();
+    const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
+    const bool full = ti.x0 >= ti.s.head && ti.x0 + R * kRoundBytes <= ti.s.valid_end;
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) m[k] = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        uint32_t mask = 0xFFFFu;
+        if (FILTER) {
+            // Bytes 16..19 of the lane are the next lane's first word; for the
+            // last lane, the next round's lane 0 (read wave-wide, before any
+            // divergence) or the word after the tile.
+            const uint32_t next0 = (k + 1 < R) ? __builtin_amdgcn_readfirstlane(r.v[(k + 1) % R].x) : r.extra;
+            uint32_t nx = __shfl_down(r.v[k].x, 1);
+            if (lane == kWave - 1) nx = next0;
+            const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
+            mask = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
+                                           : w[u >> 2];
+                mask |= probe<K, Q4>(bm, g, qmask, sh) << u;
+                if ((u & 3) == 3) {
+                    // Finish these probes here (see tile_hits4).
+                    __asm__ volatile("" : "+v"(mask));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+        m[k / 2] |= mask << (16 * (k % 2));
+        // Keep rounds apart: interleaving all probes of the tile costs more
+        // registers than the wave has.
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int R, class Sink>
+__device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, const TileInfo &ti,
+                                              const uint32_t (&m)[R / 2], const uint8_t *cls, uint16_t *queue,
+                                              Sink &sink) {
+    const uint32_t lane = lane_id();
+    uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+        if (__ballot(mask != 0) == 0) continue;
+        uint32_t tot;
+        uint32_t pos = qtail + wave_prefix_small<5>((uint32_t)__popc(mask), tot);
+        const uint32_t base = (uint32_t)k * kRoundBytes + lane * 16u;
+        while (mask) {
+            const uint32_t u = (uint32_t)__builtin_ctz(mask);
+            mask &= mask - 1u;
+            queue[(pos++) & (kRing1 - 1)] = (uint16_t)(base + u);
+        }
+        qtail += tot;
+        wave_lds_sync();
+        for (; qtail - qhead >= (uint32_t)kWave; qhead += kWave) {
+            const uint32_t off = queue[(qhead + lane) & (kRing1 - 1)];
+            const uint32_t last = walk(P.d, ti.s, cls, ti.x0 + off);
+            sink.batch(P, t, ti, off, last);
+        }
+    }
+    if (qtail != qhead) {
+        const uint32_t n = qtail - qhead;
+        const bool act = lane < n;
+        const uint32_t off = act ? queue[(qhead + lane) & (kRing1 - 1)] : 0u;
+        const uint32_t last = act ? walk(P.d, ti.s, cls, ti.x0 + off) : 0u;
+        sink.batch(P, t, ti, off, last);
+    }
+    sink.finish(t);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Filter then walk one tile already in registers, walks right away.
+template <int STRIDE, bool FILTER, int K, bool Q4, int R, class Sink>
+__device__ __forceinline__ void scan_loaded_tile(const ScanParams &P, uint64_t t, const TileInfo &ti,
+                                                 const TileRegs<R> &r, const uint32_t *bm, const uint8_t *cls,
+                                                 uint16_t *queue, Sink &sink) {
+    if constexpr (STRIDE == 4) {
+        HitBits<R> pbits;
+        uint32_t xb;
+        tile_hits4<R, K, Q4>(P.d, r, bm, pbits, xb);
+        walk_hits4<R>(P, t, ti, pbits, xb, cls, queue, sink);
+    } else {
+        uint32_t m[R / 2];
+        tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, m);
+        walk_offsets1<R>(P, t, ti, m, cls, queue, sink);
+    }
+}
+
+// Copy the bitmap and byte classes into LDS.
+template <bool FILTER>
+__device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, uint8_t *cls) {
+    if (FILTER) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.bitmap);
+        uint4 *dst = reinterpret_cast<uint4 *>(bm);
+        for (uint32_t k = threadIdx.x; k < P.bm_bytes / 16; k += kBlock) dst[k] = src[k];
+    }
+    if (threadIdx.x < 64)
+        reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
+}
+
+template <bool BATCH>
+__device__ __forceinline__ uint64_t total_tiles(const ScanParams &P) {
+    return BATCH ? P.meta[kMetaTiles] : P.ntiles;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ uint64_t total_items(const ScanParams &P) {
+    return BATCH ? P.meta[kMetaItems] : (uint64_t)gridDim.x;
+}
+
+template <int STRIDE, bool FILTER, int K, bool Q4, int R, bool BATCH>
+__global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
+    constexpr int TILE = R * kRoundBytes;
+    constexpr bool kDefer = STRIDE == 4;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t hl_count, hl_claimed;
+    __shared__ uint64_t item_sh;
+    __shared__ uint64_t red[kWaves];
+    const LdsLayout<STRIDE> Lo{P.bm_bytes};
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
+    uint8_t *cls = lds + Lo.cls_off();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
+    uint32_t *nm_l = reinterpret_cast<uint32_t *>(lds + Lo.nm_off());
+    uint64_t *rec_l = reinterpret_cast<uint64_t *>(lds + Lo.rec_off());
+    const HitList HL{reinterpret_cast<uint32_t *>(lds + Lo.hits_off()), &hl_count, &hl_claimed};
+
+    // One text: the emit kernel adds into the counts after this kernel ends.
+    // (A batch's prep kernel zeroes them.)
+    if (!BATCH)
+        for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < P.d.num_patterns;
+             k += (uint64_t)gridDim.x * kBlock)
+            P.counts[k] = 0;
+    stage_tables<FILTER>(P, bm, cls);
+
+    const uint64_t nt = total_tiles<BATCH>(P);
+    for (uint32_t round = 0;; ++round) {
+        // Next work item: a device ticket for a batch, the block index otherwise.
+        if (threadIdx.x == 0)
+            item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull)
+                            : (round == 0 ? (uint64_t)blockIdx.x : ~0ull);
+        for (uint32_t k = threadIdx.x; k < kMaxTilesPerItem; k += kBlock) {
+            nm_l[k] = 0;
+            rec_l[k] = 0;
+        }
+        if (kDefer) {
+            for (uint32_t k = threadIdx.x; k < kHitCap; k += kBlock) HL.hits[k] = kHitFree;
+            if (threadIdx.x == 0) hl_count = hl_claimed = 0;
+        }
+        __syncthreads();
+        const uint64_t item = item_sh;
+        if (item >= total_items<BATCH>(P)) break;
+        const uint64_t tb = item * P.tiles_per_item;
+        const uint64_t te = min(nt, tb + P.tiles_per_item);
+
+        // Pipelined: once a tile's filter bits are known its bytes are dead,
+        // so the next tile's loads go out before anything else.
+        TileRegs<R> r;
+        TileInfo cur{};
+        uint64_t t = tb + wave;
+        if (t < te) {
+            cur = tile_info<BATCH, TILE>(P, t);
+            load_tile<R, FILTER>(cur, r);
+        }
+        for (; t < te; t += kWaves) {
+            const bool has_next = t + kWaves < te;
+            TileInfo nxt = cur;
+            if (has_next) nxt = tile_info<BATCH, TILE>(P, t + kWaves);
+            StageSink sink(nm_l, rec_l, tb);
+            if constexpr (STRIDE == 4) {
+                HitBits<R> pbits;
+                uint32_t xb;
+                tile_hits4<R, K, Q4>(P.d, r, bm, pbits, xb);
+                if (has_next) load_tile<R, FILTER>(nxt, r);
+                if (__ballot(pbits != 0) != 0 || xb) {
+                    if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
+                        walk_hits4<R>(P, t, cur, pbits, xb, cls, queue, sink);
+                }
+                claim_and_walk<BATCH, TILE>(P, HL, tb, cls, nm_l, rec_l);
+            } else {
+                uint32_t m[R / 2];
+                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, m);
+                if (has_next) load_tile<R, FILTER>(nxt, r);
+                walk_offsets1<R>(P, t, cur, m, cls, queue, sink);
+            }
+            cur = nxt;
+        }
+        if (kDefer) {
+            // The rest of the list, shared by all waves.
+            __syncthreads();
+            const uint32_t n = hl_count, c0 = hl_claimed;
+            for (uint32_t f = c0 + wave * 16u; f < n; f += kWaves * 16u)
+                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, cls, nm_l, rec_l);
+        }
+        __syncthreads();
+        // The item's tile results, coalesced, and its total.
+        uint64_t part = 0;
+        for (uint64_t k = tb + threadIdx.x; k < te; k += kBlock) {
+            const uint64_t rc = rec_l[k - tb];
+            P.tile_rec[k] = rc;
+            P.tile_nm[k] = nm_l[k - tb];
+            part += rc;
+        }
+        part = block_sum_u64(part, red);
+        if (threadIdx.x == 0) P.itemsum[item] = part;
+    }
+}
+
+template <int STRIDE, bool FILTER, int K, bool Q4, int R, bool BATCH>
+__global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitParams E) {
+    constexpr int TILE = R * kRoundBytes;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint64_t scan_sh[kWaves + 1];
+    __shared__ uint64_t red[kWaves];
+    __shared__ uint32_t n_over, any_over;
+    __shared__ uint64_t over_tile[kBlock];
+    __shared__ uint64_t over_base[kBlock];
+    const LdsLayout<STRIDE> Lo{P.bm_bytes};
+    uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
+    uint8_t *cls = lds + Lo.cls_off();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
+    const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
+    bool staged = false;
+
+    for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
+        const uint64_t tb = item * P.tiles_per_item;
+        const uint64_t te = min(nt, tb + P.tiles_per_item);
+        // Records of all earlier items, and whether any tile here overflowed.
+        uint64_t part = 0;
+        for (uint64_t g = threadIdx.x; g < item; g += kBlock) part += P.itemsum[g];
+        uint32_t over = 0;
+        for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
+        if (threadIdx.x == 0) any_over = 0;
+        uint64_t base = block_sum_u64(part, red);
+        if (over) atomicOr(&any_over, 1u);
+        __syncthreads();
+        if (any_over && !staged) {
+            stage_tables<FILTER>(P, bm, cls);
+            staged = true;
+            __syncthreads();
+        }
+
+        for (uint64_t c0 = tb; c0 < te; c0 += kBlock) {
+            const uint64_t t = c0 + threadIdx.x;
+            const bool in = t < te;
+            const uint64_t rec = in ? P.tile_rec[t] : 0ull;
+            uint64_t chunk_total;
+            const uint64_t tile_base = base + block_excl_scan_u64(rec, scan_sh, chunk_total);
+            if (threadIdx.x == 0) n_over = 0;
+            __syncthreads();
+            if (in) {
+                const TileInfo ti = tile_info<BATCH, TILE>(P, t);
+                if (BATCH && t == P.tile_start[ti.chunk]) E.chunk_first[ti.chunk] = tile_base;
+                const uint32_t nm = rec > 0 ? P.tile_nm[t] : 0u;
+                if (nm > kStageCap) {
+                    const uint32_t slot = atomicAdd(&n_over, 1u);
+                    over_tile[slot] = t;
+                    over_base[slot] = tile_base;
+                } else if (nm > 0) {
+                    // Staged starts, in ascending offset (slots may be
+                    // unordered; offsets are distinct, so the smallest entry
+                    // above the last one written is the next).
+                    uint64_t pos = tile_base;
+                    uint64_t prev = 0;
+                    for (uint32_t e = 0; e < nm; ++e) {
+                        uint64_t ent = ~0ull;
+                        for (uint32_t j = 0; j < nm; ++j) {
+                            const uint64_t c = P.staging[t * kStageCap + j];
+                            if ((e == 0 || c > prev) && c < ent) ent = c;
+                        }
+                        prev = ent;
+                        const uint32_t st = (uint32_t)ent;
+                        const uint64_t i = ti.x0 + (ent >> 32) - ti.s.head;
+                        const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
+                        for (uint32_t k = 0; k < cnt; ++k, ++pos) {
+                            const uint32_t id = P.d.outids[first + k];
+                            if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
+                            atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t o = wave; o < n_over; o += kWaves) {
+                const uint64_t ot = over_tile[o];
+                const TileInfo ti = tile_info<BATCH, TILE>(P, ot);
+                TileRegs<R> r;
+                load_tile<R, FILTER>(ti, r);
+                DirectSink sink(&E, over_base[o]);
+                scan_loaded_tile<STRIDE, FILTER, K, Q4, R>(P, ot, ti, r, bm, cls, queue, sink);
+            }
+            __syncthreads();
+            base += chunk_total;
+        }
+        if (item == items - 1 && threadIdx.x == 0) {
+            if (E.total) *E.total = base;
+            if (BATCH) P.meta[kMetaTotal] = base;
+        }
+    }
+}
+
+template <int = 0>
+__global__ void glop_zero_kernel(uint64_t *counts, uint32_t n, uint64_t *total) {
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) counts[k] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0;
+}
+
+// Batch prep (one workgroup): tiles per chunk -> first tile of each chunk,
+// total tiles and work items, a zero ticket, zero counts.  Every chunk gets at
+// least one tile, so each has a first tile to report its output position.
+template <int TILE>
+__global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P) {
+    __shared__ uint64_t sh[kWaves + 1];
+    uint64_t running = 0;
+    for (uint64_t c0 = 0; c0 < P.nchunks; c0 += kBlock) {
+        const uint64_t c = c0 + threadIdx.x;
+        uint64_t nt = 0;
+        if (c < P.nchunks) {
+            const glop_chunk_t ch = P.chunks[c];
+            const uint64_t span = (reinterpret_cast<uintptr_t>(ch.text) & 15u) + ch.len;
+            nt = span ? (span + TILE - 1) / TILE : 1;
+        }
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan_u64(nt, sh, tot);
+        if (c < P.nchunks) P.tile_start[c] = running + ex;
+        running += tot;
+    }
+    if (threadIdx.x == 0) {
+        P.tile_start[P.nchunks] = running;
+        const bool overflow = running > P.tile_cap;
+        P.meta[kMetaTiles] = overflow ? 0 : running;
+        P.meta[kMetaItems] = overflow ? 0 : (running + P.tiles_per_item - 1) / P.tiles_per_item;
+        P.meta[kMetaTicket] = 0;
+        P.meta[kMetaOverflow] = overflow ? 1 : 0;
+        P.meta[kMetaTotal] = 0;
+    }
+    for (uint32_t k = threadIdx.x; k < P.d.num_patterns; k += kBlock) P.counts[k] = 0;
+}
+
+// Batch: chunk of every tile (binary search in the first-tile table).
+template <int = 0>
+__global__ void glop_batch_map_kernel(ScanParams P) {
+    const uint64_t nt = P.meta[kMetaTiles];
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = P.nchunks;  // answer in [lo, hi)
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (P.tile_start[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        P.tile_chunk[t] = lo;
+    }
+}
+
+// Batch: occurrences per chunk, the total, and the overflow verdict.
+template <int = 0>
+__global__ void glop_batch_finish_kernel(ScanParams P, uint64_t *chunk_first, uint64_t *chunk_count,
+                                         uint64_t *total) {
+    const bool overflow = P.meta[kMetaOverflow] != 0;
+    const uint64_t tot = P.meta[kMetaTotal];
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P.nchunks;
+         c += (uint64_t)gridDim.x * blockDim.x) {
+        if (overflow) {
+            chunk_first[c] = 0;
+            chunk_count[c] = 0;
+        } else {
+            const uint64_t next = c + 1 < P.nchunks ? chunk_first[c + 1] : tot;
+            chunk_count[c] = next - chunk_first[c];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = overflow ? ~0ull : tot;
+}
+
+constexpr uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+struct Geometry {
+    uint64_t ntiles, tiles_per_item;
+    uint32_t grid;
+    uint64_t off_rec, off_nm, off_stage, off_item, bytes;
+};
+
+// One text: tiles of `tile` bytes, at most kMaxTilesPerItem per workgroup.
+inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile) {
+    Geometry g{};
+    g.ntiles = (len + 15 + tile - 1) / tile;  // the text plus up to 15 leading alignment bytes
+    const uint64_t wgs = (uint64_t)(num_cus > 0 ? num_cus : 1);
+    g.tiles_per_item = g.ntiles ? (g.ntiles + wgs - 1) / wgs : 1;
+    if (g.tiles_per_item > kMaxTilesPerItem) g.tiles_per_item = kMaxTilesPerItem;
+    g.grid = (uint32_t)(g.ntiles ? (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item : 0);
+    g.off_rec = 0;
+    g.off_nm = align256(g.off_rec + g.ntiles * 8);
+    g.off_stage = align256(g.off_nm + g.ntiles * 4);
+    g.off_item = align256(g.off_stage + g.ntiles * kStageCap * 8);
+    g.bytes = align256(g.off_item + (uint64_t)g.grid * 8);
+    if (g.bytes == 0) g.bytes = 256;
+    return g;
+}
+
+struct BatchGeometry {
+    uint64_t tile_cap, item_cap;
+    uint64_t off_rec, off_nm, off_stage, off_chunk, off_start, off_item, off_meta, bytes;
+};
+
+// A batch: sized for the smallest tile, so it holds either tile size.
+inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) {
+    BatchGeometry g{};
+    g.tile_cap = (max_total_bytes + 16ull * nchunks) / kMinTileBytes + nchunks + 1;
+    g.item_cap = (g.tile_cap + kMaxTilesPerItem - 1) / kMaxTilesPerItem;
+    g.off_rec = 0;
+    g.off_nm = align256(g.off_rec + g.tile_cap * 8);
+    g.off_stage = align256(g.off_nm + g.tile_cap * 4);
+    g.off_chunk = align256(g.off_stage + g.tile_cap * kStageCap * 8);
+    g.off_start = align256(g.off_chunk + g.tile_cap * 4);
+    g.off_item = align256(g.off_start + ((uint64_t)nchunks + 1) * 8);
+    g.off_meta = align256(g.off_item + g.item_cap * 8);
+    g.bytes = align256(g.off_meta + kMetaWords * 8);
+    return g;
+}
+
+template <int STRIDE>
+constexpr size_t dyn_lds(uint32_t bm_bytes) {
+    return LdsLayout<STRIDE>{bm_bytes}.bytes();
+}
+
+template <int STRIDE, bool FILTER, int K, bool Q4, int R>
+struct Kernels {
+    static hipError_t set_lds_limit() {
+        const int bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8);
+        const void *fns[] = {reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>),
+                             reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>),
+                             reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>),
+                             reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>)};
+        for (const void *f : fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+
+    static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
+                          const glop_events_t *ev) {
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
+        hipError_t e;
+        if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (ev && ev->scan_end && (e = hipEventRecord((hipEvent_t)ev->scan_end, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P,
+                           E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (ev && ev->emit_end) e = hipEventRecord((hipEvent_t)ev->emit_end, s);
+        return e;
+    }
+
+    static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
+                            int num_cus, hipStream_t s) {
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
+        const uint32_t cus = (uint32_t)(num_cus > 0 ? num_cus : 1);
+        hipLaunchKernelGGL((glop_batch_prep_kernel<R * kRoundBytes>), dim3(1), dim3(kBlock), 0, s, P);
+        hipError_t e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(glop_batch_map_kernel<0>, dim3(4 * cus), dim3(256), 0, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>), dim3(cus), dim3(kBlock), lds, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>), dim3(cus), dim3(kBlock), lds, s, P, E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const uint32_t fb = (P.nchunks + 255) / 256 > 1024 ? 1024u : (uint32_t)((P.nchunks + 255) / 256);
+        hipLaunchKernelGGL(glop_batch_finish_kernel<0>, dim3(fb ? fb : 1), dim3(256), 0, s, P, E.chunk_first,
+                           chunk_count, total);
+        return hipGetLastError();
+    }
+};
+
+
+// Launch entry points of one Kernels<> variant.  Each variant translation unit
+// defines the tables of its variants; the dispatch only declares them, so it
+// never instantiates a kernel itself.
+struct VariantFns {
+    hipError_t (*one)(const ScanParams &, const EmitParams &, uint32_t, hipStream_t, const glop_events_t *);
+    hipError_t (*batch)(const ScanParams &, const EmitParams &, uint64_t *, uint64_t *, int, hipStream_t);
+    hipError_t (*set_lds_limit)();
+};
+
+#define GLOP_VARIANT_ID(S, F, K, Q, R) glop_variant_##S##_##F##_##K##_##Q##_##R
+#define GLOP_DECLARE_VARIANT(S, F, K, Q, R) const VariantFns &GLOP_VARIANT_ID(S, F, K, Q, R)();
+#define GLOP_DEFINE_VARIANT(S, F, K, Q, R)                                                         \
+    const VariantFns &GLOP_VARIANT_ID(S, F, K, Q, R)() {                                            \
+        static const VariantFns v = {&Kernels<S, (F != 0), K, (Q != 0), R>::one,                    \
+                                     &Kernels<S, (F != 0), K, (Q != 0), R>::batch,                  \
+                                     &Kernels<S, (F != 0), K, (Q != 0), R>::set_lds_limit};         \
+        return v;                                                                                   \
+    }
+
+}  // namespace detail
+}  // namespace glop

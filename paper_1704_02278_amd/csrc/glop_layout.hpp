@@ -59,6 +59,6 @@ struct GlopDevDict {
     uint32_t num_states;
     uint32_t num_patterns;
     uint32_t min_len, max_len;
-    uint32_t qgram, qmask, stride, bitmap_log2, probe_bits;
+    uint32_t qgram, qmask, stride, bitmap_log2, probe_bits, tile_kib;
     int32_t filter;  // GLOP_FILTER_NONE or GLOP_FILTER_QGRAM
 };

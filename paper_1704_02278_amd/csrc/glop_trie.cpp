@@ -226,6 +226,15 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             c.bitmap_log2 = 12;
             c.bitmap.assign((1u << 12) / 32, 0);
         }
+        c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
+        if (c.tile_kib != 8 && c.tile_kib != 16) {
+            err = "tile_kib must be 8 or 16";
+            return GLOP_EINVAL;
+        }
+        if (c.tile_kib == 16 && !(c.filter == GLOP_FILTER_QGRAM && c.stride == 4)) {
+            err = "16 KiB tiles need the stride-4 filter";
+            return GLOP_EINVAL;
+        }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while compiling the dictionary";
         return GLOP_ENOMEM;

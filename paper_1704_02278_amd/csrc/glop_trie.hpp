@@ -19,7 +19,7 @@ struct Compiled {
     std::vector<uint32_t> term;    // 2 * num_states
     std::vector<uint32_t> outids;  // output lists
     int32_t filter = GLOP_FILTER_NONE;
-    uint32_t qgram = 0, qmask = 0, stride = 1, bitmap_log2 = 12, probe_bits = 1;
+    uint32_t qgram = 0, qmask = 0, stride = 1, bitmap_log2 = 12, probe_bits = 1, tile_kib = 8;
     uint64_t filter_keys = 0;
     std::vector<uint32_t> bitmap;  // 2^bitmap_log2 bits
 };
