@@ -135,6 +135,10 @@ struct EmitParams {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Wave index in the workgroup, known to the compiler as wave-uniform (so the
+// tile indices and addresses derived from it live in scalar registers).
+__device__ __forceinline__ uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
@@ -178,7 +182,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Exclusive scan over the block (1024 threads); `total` = block sum.
 __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh, uint64_t &total) {
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = wave_id();
     uint64_t incl = v;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -207,7 +211,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
 
 // Sum over the block (1024 threads), returned to every thread.
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id(), wave = wave_id();
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (lane == 0) sh[wave] = v;
@@ -218,33 +222,39 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
     return s;
 }
 
-// 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
-__device__ __forceinline__ uint4 load16(const Span &s, uint64_t x) {
-    if (x >= s.head && x + 16 <= s.span_end) return *reinterpret_cast<const uint4 *>(s.abase + x);
-    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint64_t y = x + k;
-        const uint32_t b = (y >= s.head && y < s.span_end) ? (uint32_t)s.abase[y] : 0u;
-        const uint32_t sh = 8 * (k & 3);
-        if (k < 4) w0 |= b << sh;
-        else if (k < 8) w1 |= b << sh;
-        else if (k < 12) w2 |= b << sh;
-        else w3 |= b << sh;
-    }
-    return make_uint4(w0, w1, w2, w3);
+// Zero the bytes of little-endian word w (coordinates x .. x+3) outside [lo, hi).
+__device__ __forceinline__ uint32_t keep_bytes(uint32_t w, int64_t x, int64_t lo, int64_t hi) {
+    int64_t a = lo - x, b = hi - x;  // keep byte k iff a <= k < b
+    a = a < 0 ? 0 : (a > 4 ? 4 : a);
+    b = b < 0 ? 0 : (b > 4 ? 4 : b);
+    if (b <= a) return 0u;
+    const uint32_t hi_mask = b == 4 ? 0xFFFFFFFFu : ((1u << (8 * b)) - 1u);
+    const uint32_t lo_mask = a == 0 ? 0u : ((1u << (8 * a)) - 1u);
+    return w & hi_mask & ~lo_mask;
 }
 
-// 4 text bytes at aligned coordinate x (multiple of 4); outside reads as 0.
+// 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
+// An aligned 16-byte block holding at least one text byte lies in the same
+// page as that byte, so it is read whole and the outside bytes are masked;
+// a block holding none is not read.
+__device__ __forceinline__ uint4 load16(const Span &s, uint64_t x) {
+    if (x + 16 <= s.head || x >= s.span_end) return make_uint4(0u, 0u, 0u, 0u);
+    uint4 v = *reinterpret_cast<const uint4 *>(s.abase + x);
+    if (x >= s.head && x + 16 <= s.span_end) return v;
+    const int64_t lo = (int64_t)s.head, hi = (int64_t)s.span_end, xi = (int64_t)x;
+    v.x = keep_bytes(v.x, xi, lo, hi);
+    v.y = keep_bytes(v.y, xi + 4, lo, hi);
+    v.z = keep_bytes(v.z, xi + 8, lo, hi);
+    v.w = keep_bytes(v.w, xi + 12, lo, hi);
+    return v;
+}
+
+// 4 text bytes at aligned coordinate x (multiple of 4); outside reads as 0
+// (same rule as load16).
 __device__ __forceinline__ uint32_t load4(const Span &s, uint64_t x) {
-    if (x >= s.head && x + 4 <= s.span_end) return *reinterpret_cast<const uint32_t *>(s.abase + x);
-    uint32_t w = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t y = x + k;
-        w |= ((y >= s.head && y < s.span_end) ? (uint32_t)s.abase[y] : 0u) << (8 * k);
-    }
-    return w;
+    if (x + 4 <= s.head || x >= s.span_end) return 0u;
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(s.abase + x);
+    return keep_bytes(w, (int64_t)x, (int64_t)s.head, (int64_t)s.span_end);
 }
 
 // Bloom probe: 1 if every probe bit of q-gram g is set.
@@ -312,7 +322,7 @@ struct TileInfo {
     Span s;
     uint64_t x0;
     uint32_t chunk;
-    bool interior;
+    uint32_t interior;  // 1: every byte the tile loads is inside its text
 };
 
 template <bool BATCH, int TILE>
@@ -329,7 +339,7 @@ __device__ __forceinline__ TileInfo tile_info(const ScanParams &P, uint64_t t) {
         ti.s = P.one;
     }
     ti.x0 = k * (uint64_t)TILE;
-    ti.interior = ti.x0 >= ti.s.head && ti.x0 + TILE + 4 <= ti.s.span_end;
+    ti.interior = (ti.x0 >= ti.s.head && ti.x0 + TILE + 4 <= ti.s.span_end) ? 1u : 0u;
     return ti;
 }
 
@@ -739,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = wave_id();
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     uint32_t *nm_l = reinterpret_cast<uint32_t *>(lds + Lo.nm_off());
     uint64_t *rec_l = reinterpret_cast<uint64_t *>(lds + Lo.rec_off());
@@ -838,7 +848,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = wave_id();
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
     bool staged = false;
