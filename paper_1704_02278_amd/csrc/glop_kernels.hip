@@ -106,6 +106,7 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.chunks = a.chunks;
     P.nchunks = a.nchunks;
     P.tile_cap = g.tile_cap;
+    P.item_cap = g.item_cap;
     P.tiles_per_item = kMaxTilesPerItem;
     uint8_t *ws = static_cast<uint8_t *>(a.workspace);
     P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);

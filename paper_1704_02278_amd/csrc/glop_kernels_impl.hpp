@@ -71,7 +71,15 @@ constexpr uint32_t kPosBits = 15;
 constexpr uint32_t kMaxTilesPerItem = 512;
 
 // Batch metadata words in the workspace.
-enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaWords = 8 };
+enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaError = 5, kMetaWords = 8 };
+
+// A listed hit word is written right after its space is reserved; a walker
+// waits for it at most this many short sleeps (about 0.1 s) before giving up
+// and failing the call, so no wave can wait forever.
+constexpr uint32_t kSpinLimit = 1u << 22;
+// Record total of a work item that failed; the emit kernel then reports the
+// call's total as UINT64_MAX.
+constexpr uint64_t kItemFailed = ~0ull;
 
 template <int STRIDE>
 constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
@@ -117,6 +125,7 @@ struct ScanParams {
     uint32_t *tile_chunk;        // batch: chunk of each tile
     uint64_t *meta;              // batch: kMeta* words
     uint64_t tile_cap;           // batch: tiles the workspace holds
+    uint64_t item_cap;           // batch: work items the workspace holds
     uint64_t tiles_per_item;
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
     uint64_t *tile_rec;          // records per tile
@@ -569,16 +578,25 @@ __device__ __forceinline__ bool list_hits(const HitList &L, uint32_t t_rel, HitB
 // particular order (the emit kernel sorts them).
 template <bool BATCH, int TILE>
 __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &L, uint32_t first, uint32_t n,
-                                            uint64_t tb, const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l) {
+                                            uint64_t tb, const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l,
+                                            uint32_t *failed) {
     const uint32_t lane = lane_id();
     const uint32_t h = lane >> 2;
     bool act = h < n;
     uint32_t ent = 0;
     if (act) {
-        // Every reserved entry is written right after its reservation.
-        while ((ent = __hip_atomic_load(&L.hits[first + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) ==
-               kHitFree)
+        // Every reserved entry is written right after its reservation; the
+        // wait is bounded all the same.
+        for (uint32_t spin = 0;; ++spin) {
+            ent = __hip_atomic_load(&L.hits[first + h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (ent != kHitFree) break;
+            if (spin == kSpinLimit) {
+                atomicOr(failed, 1u);
+                act = false;
+                break;
+            }
             __builtin_amdgcn_s_sleep(1);
+        }
     }
     const uint32_t t_rel = ent >> kPosBits;
     const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
@@ -599,7 +617,8 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
 // Take 16 listed hit words if that many are waiting, and walk them.
 template <bool BATCH, int TILE>
 __device__ __forceinline__ void claim_and_walk(const ScanParams &P, const HitList &L, uint64_t tb,
-                                               const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l) {
+                                               const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l,
+                                               uint32_t *failed) {
     uint32_t got = 0, first = 0;
     if (lane_id() == 0) {
         uint32_t c = __hip_atomic_load(L.claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -615,7 +634,7 @@ __device__ __forceinline__ void claim_and_walk(const ScanParams &P, const HitLis
     }
     got = __builtin_amdgcn_readfirstlane(got);
     first = __builtin_amdgcn_readfirstlane(first);
-    if (got) walk_listed<BATCH, TILE>(P, L, first, 16u, tb, cls, nm_l, rec_l);
+    if (got) walk_listed<BATCH, TILE>(P, L, first, 16u, tb, cls, nm_l, rec_l, failed);
 }
 
 // ---- stride 1: one probe per offset (or none: walk every offset) ----------
@@ -728,14 +747,16 @@ __device__ __forceinline__ void stage_tables(const ScanParams &P, uint32_t *bm, 
         reinterpret_cast<uint32_t *>(cls)[threadIdx.x] = reinterpret_cast<const uint32_t *>(P.d.cls)[threadIdx.x];
 }
 
+// A batch's counts come from device memory; they are clamped to what the
+// workspace holds so that no loop can run past it.
 template <bool BATCH>
 __device__ __forceinline__ uint64_t total_tiles(const ScanParams &P) {
-    return BATCH ? P.meta[kMetaTiles] : P.ntiles;
+    return BATCH ? min(P.meta[kMetaTiles], P.tile_cap) : P.ntiles;
 }
 
 template <bool BATCH>
 __device__ __forceinline__ uint64_t total_items(const ScanParams &P) {
-    return BATCH ? P.meta[kMetaItems] : (uint64_t)gridDim.x;
+    return BATCH ? min(P.meta[kMetaItems], P.item_cap) : (uint64_t)gridDim.x;
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R, bool BATCH>
@@ -743,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
     constexpr bool kDefer = STRIDE == 4;
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t hl_count, hl_claimed;
+    __shared__ uint32_t hl_count, hl_claimed, item_failed;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
@@ -777,6 +798,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             for (uint32_t k = threadIdx.x; k < kHitCap; k += kBlock) HL.hits[k] = kHitFree;
             if (threadIdx.x == 0) hl_count = hl_claimed = 0;
         }
+        if (threadIdx.x == 0) item_failed = 0;
         __syncthreads();
         const uint64_t item = item_sh;
         if (item >= total_items<BATCH>(P)) break;
@@ -806,7 +828,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                     if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
                         walk_hits4<R>(P, t, cur, pbits, xb, cls, queue, sink);
                 }
-                claim_and_walk<BATCH, TILE>(P, HL, tb, cls, nm_l, rec_l);
+                claim_and_walk<BATCH, TILE>(P, HL, tb, cls, nm_l, rec_l, &item_failed);
             } else {
                 uint32_t m[R / 2];
                 tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, m);
@@ -820,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             __syncthreads();
             const uint32_t n = hl_count, c0 = hl_claimed;
             for (uint32_t f = c0 + wave * 16u; f < n; f += kWaves * 16u)
-                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, cls, nm_l, rec_l);
+                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, cls, nm_l, rec_l, &item_failed);
         }
         __syncthreads();
         // The item's tile results, coalesced, and its total.
@@ -832,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             part += rc;
         }
         part = block_sum_u64(part, red);
-        if (threadIdx.x == 0) P.itemsum[item] = part;
+        if (threadIdx.x == 0) P.itemsum[item] = item_failed ? kItemFailed : part;
     }
 }
 
@@ -842,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint64_t scan_sh[kWaves + 1];
     __shared__ uint64_t red[kWaves];
-    __shared__ uint32_t n_over, any_over;
+    __shared__ uint32_t n_over, any_over, any_failed;
     __shared__ uint64_t over_tile[kBlock];
     __shared__ uint64_t over_base[kBlock];
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
@@ -852,13 +874,23 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
     bool staged = false;
+    if (threadIdx.x == 0) any_failed = 0;
+    __syncthreads();
 
     for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const uint64_t tb = item * P.tiles_per_item;
         const uint64_t te = min(nt, tb + P.tiles_per_item);
         // Records of all earlier items, and whether any tile here overflowed.
+        // A failed item (kItemFailed) fails the whole call.
         uint64_t part = 0;
-        for (uint64_t g = threadIdx.x; g < item; g += kBlock) part += P.itemsum[g];
+        uint32_t bad = 0;
+        const uint64_t upto = item == items - 1 ? items : item;  // the last item also checks itself
+        for (uint64_t g = threadIdx.x; g < upto; g += kBlock) {
+            const uint64_t v = P.itemsum[g];
+            bad |= v == kItemFailed;
+            if (g < item) part += v;
+        }
+        if (bad) atomicOr(&any_failed, 1u);
         uint32_t over = 0;
         for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
         if (threadIdx.x == 0) any_over = 0;
@@ -923,9 +955,13 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             __syncthreads();
             base += chunk_total;
         }
+        __syncthreads();
         if (item == items - 1 && threadIdx.x == 0) {
-            if (E.total) *E.total = base;
-            if (BATCH) P.meta[kMetaTotal] = base;
+            if (E.total) *E.total = any_failed ? ~0ull : base;
+            if (BATCH) {
+                P.meta[kMetaTotal] = base;
+                if (any_failed) P.meta[kMetaError] = 1;
+            }
         }
     }
 }
@@ -964,6 +1000,7 @@ __global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P) {
         P.meta[kMetaTicket] = 0;
         P.meta[kMetaOverflow] = overflow ? 1 : 0;
         P.meta[kMetaTotal] = 0;
+        P.meta[kMetaError] = 0;
     }
     for (uint32_t k = threadIdx.x; k < P.d.num_patterns; k += kBlock) P.counts[k] = 0;
 }
@@ -971,7 +1008,7 @@ __global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P) {
 // Batch: chunk of every tile (binary search in the first-tile table).
 template <int = 0>
 __global__ void glop_batch_map_kernel(ScanParams P) {
-    const uint64_t nt = P.meta[kMetaTiles];
+    const uint64_t nt = min(P.meta[kMetaTiles], P.tile_cap);
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
          t += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t lo = 0, hi = P.nchunks;  // answer in [lo, hi)
@@ -988,7 +1025,7 @@ __global__ void glop_batch_map_kernel(ScanParams P) {
 template <int = 0>
 __global__ void glop_batch_finish_kernel(ScanParams P, uint64_t *chunk_first, uint64_t *chunk_count,
                                          uint64_t *total) {
-    const bool overflow = P.meta[kMetaOverflow] != 0;
+    const bool overflow = P.meta[kMetaOverflow] != 0 || P.meta[kMetaError] != 0;
     const uint64_t tot = P.meta[kMetaTotal];
     for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < P.nchunks;
          c += (uint64_t)gridDim.x * blockDim.x) {
@@ -1024,7 +1061,6 @@ inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile) {
     g.off_stage = align256(g.off_nm + g.ntiles * 4);
     g.off_item = align256(g.off_stage + g.ntiles * kStageCap * 8);
     g.bytes = align256(g.off_item + (uint64_t)g.grid * 8);
-    if (g.bytes == 0) g.bytes = 256;
     return g;
 }
 
