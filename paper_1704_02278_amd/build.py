@@ -8,12 +8,16 @@
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
+sys.path.insert(0, str(PKG))
+import isa_check  # noqa: E402  (a sibling module; the package itself is not imported)
+
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libglop.so"
@@ -33,16 +37,33 @@ def build(verbose: bool = False) -> Path:
     objdir.mkdir(exist_ok=True)
     def compile_one(src):
         obj = objdir / (src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        device = src.endswith(".hip")
+        # Device sources keep their assembly (-save-temps, same compile) so
+        # that every kernel can be checked for barriers in divergent loops.
+        temps = objdir / (src + ".temps")
+        if device:
+            shutil.rmtree(temps, ignore_errors=True)
+            temps.mkdir()
+        lang = ["-x", "hip", "-save-temps"] if device else []
         cmd = [HIPCC, *DEVICE_FLAGS, *COMMON_FLAGS, *lang, "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
+        res = subprocess.run(cmd, capture_output=True, text=True, cwd=str(temps) if device else None)
         errs = "\n".join(l for l in (res.stderr or "").splitlines() if "packed-fp32-ops" not in l)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{errs}")
         if errs.strip() and verbose:
             print(errs, file=sys.stderr)
+        if device:
+            problems = []
+            for asm in sorted(temps.glob("*-hip-amdgcn-amd-amdhsa-gfx950.s")):
+                for kernel, probs in isa_check.check_file(asm).items():
+                    problems += [f"{src}: {kernel}: {p}" for p in probs]
+            if not any(temps.glob("*-hip-amdgcn-amd-amdhsa-gfx950.s")):
+                raise RuntimeError(f"no device assembly kept for {src}")
+            shutil.rmtree(temps, ignore_errors=True)
+            if problems:
+                raise RuntimeError("kernel check failed:\n" + "\n".join(problems))
         return str(obj)
 
     jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))

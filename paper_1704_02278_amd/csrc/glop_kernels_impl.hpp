@@ -759,6 +759,17 @@ __device__ __forceinline__ uint64_t total_items(const ScanParams &P) {
     return BATCH ? min(P.meta[kMetaItems], P.item_cap) : (uint64_t)gridDim.x;
 }
 
+// Clear a work item's LDS tile counters (and hit list at stride 4).
+template <bool DEFER>
+__device__ __forceinline__ void reset_item_lds(uint32_t *nm_l, uint64_t *rec_l, uint32_t *hits) {
+    for (uint32_t k = threadIdx.x; k < kMaxTilesPerItem; k += kBlock) {
+        nm_l[k] = 0;
+        rec_l[k] = 0;
+    }
+    if (DEFER)
+        for (uint32_t k = threadIdx.x; k < kHitCap; k += kBlock) hits[k] = kHitFree;
+}
+
 template <int STRIDE, bool FILTER, int K, bool Q4, int R, bool BATCH>
 __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
@@ -785,20 +796,20 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     stage_tables<FILTER>(P, bm, cls);
 
     const uint64_t nt = total_tiles<BATCH>(P);
-    for (uint32_t round = 0;; ++round) {
-        // Next work item: a device ticket for a batch, the block index otherwise.
-        if (threadIdx.x == 0)
-            item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull)
-                            : (round == 0 ? (uint64_t)blockIdx.x : ~0ull);
-        for (uint32_t k = threadIdx.x; k < kMaxTilesPerItem; k += kBlock) {
-            nm_l[k] = 0;
-            rec_l[k] = 0;
-        }
-        if (kDefer) {
-            for (uint32_t k = threadIdx.x; k < kHitCap; k += kBlock) HL.hits[k] = kHitFree;
-            if (threadIdx.x == 0) hl_count = hl_claimed = 0;
-        }
-        if (threadIdx.x == 0) item_failed = 0;
+    // First work item: a device ticket for a batch, the block index otherwise.
+    // Later items are taken at the end of each round, before its closing
+    // barrier: every thread-0 step sits between two barriers of the same
+    // round, so the compiler cannot route thread 0 around the loop on its own
+    // (a wave whose lanes split across rounds would pass the barrier without
+    // its lane 0 and never see the next ticket).
+    if (threadIdx.x == 0) {
+        item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull)
+                        : (uint64_t)blockIdx.x;
+        item_failed = 0;
+        if (kDefer) hl_count = hl_claimed = 0;
+    }
+    reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
+    for (;;) {
         __syncthreads();
         const uint64_t item = item_sh;
         if (item >= total_items<BATCH>(P)) break;
@@ -854,7 +865,13 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             part += rc;
         }
         part = block_sum_u64(part, red);
-        if (threadIdx.x == 0) P.itemsum[item] = item_failed ? kItemFailed : part;
+        if (threadIdx.x == 0) {
+            P.itemsum[item] = item_failed ? kItemFailed : part;
+            item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull) : ~0ull;
+            item_failed = 0;
+            if (kDefer) hl_count = hl_claimed = 0;
+        }
+        reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
     }
 }
 
@@ -873,10 +890,13 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     const uint32_t wave = wave_id();
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
-    bool staged = false;
-    if (threadIdx.x == 0) any_failed = 0;
+    bool staged = false, has_last = false;
+    uint64_t last_total = 0;
+    if (threadIdx.x == 0) any_failed = any_over = 0;
     __syncthreads();
 
+    // Thread-0 steps inside the loop sit between barriers of the same item
+    // (see the scan kernel); the call's total is written after the loop.
     for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
         const uint64_t tb = item * P.tiles_per_item;
         const uint64_t te = min(nt, tb + P.tiles_per_item);
@@ -893,10 +913,8 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         if (bad) atomicOr(&any_failed, 1u);
         uint32_t over = 0;
         for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
-        if (threadIdx.x == 0) any_over = 0;
-        uint64_t base = block_sum_u64(part, red);
         if (over) atomicOr(&any_over, 1u);
-        __syncthreads();
+        uint64_t base = block_sum_u64(part, red);  // its barriers publish any_over
         if (any_over && !staged) {
             stage_tables<FILTER>(P, bm, cls);
             staged = true;
@@ -955,13 +973,18 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             __syncthreads();
             base += chunk_total;
         }
+        if (item == items - 1) {
+            has_last = true;
+            last_total = base;
+        }
+        if (threadIdx.x == 0) any_over = 0;  // every read of it preceded the last barrier
         __syncthreads();
-        if (item == items - 1 && threadIdx.x == 0) {
-            if (E.total) *E.total = any_failed ? ~0ull : base;
-            if (BATCH) {
-                P.meta[kMetaTotal] = base;
-                if (any_failed) P.meta[kMetaError] = 1;
-            }
+    }
+    if (has_last && threadIdx.x == 0) {
+        if (E.total) *E.total = any_failed ? ~0ull : last_total;
+        if (BATCH) {
+            P.meta[kMetaTotal] = last_total;
+            if (any_failed) P.meta[kMetaError] = 1;
         }
     }
 }

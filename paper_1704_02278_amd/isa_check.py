@@ -1,0 +1,136 @@
+"""Check the gfx950 assembly of the kernels for barriers in divergent loops.
+
+A workgroup barrier (s_barrier) is counted per wave: a wave arrives when its
+active lanes reach it.  If the compiler gives a loop that holds a barrier a
+divergent exit (some lanes of a wave leave the loop while the others go round
+again), the lanes that stayed pass the barrier without the ones that left, and
+any value those lanes publish for the next iteration is never seen: the
+workgroup can spin for ever.  The optimizer produces such loops from code like
+
+    for (;;) {
+        if (threadIdx.x == 0) next = fetch();   // head
+        __syncthreads();
+        ...
+        if (threadIdx.x == 0) publish();        // tail
+    }
+
+by threading the tail's branch straight into the head's.  This module reads
+the assembly that hipcc writes with ``-save-temps`` (its loop annotations name
+every block's innermost loop and every loop's parent) and reports each loop
+that holds a barrier and also removes lanes from exec
+(``s_andn2_b64 exec, exec, ...``) in one of its own blocks.
+
+    python paper_1704_02278_amd/isa_check.py file.s [...]
+"""
+
+from __future__ import annotations
+
+import re
+import sys
+from pathlib import Path
+
+_FUNC = re.compile(r"^([A-Za-z_][\w.$]*):\s*;\s*@")
+_END = re.compile(r"^\.Lfunc_end\d+:")
+_LABEL = re.compile(r"^(\.LBB\d+_\d+):|^; %bb\.(\d+):")
+_HEADER = re.compile(r"=>\s*This (?:Inner )?Loop Header: Depth=(\d+)")
+_IN_LOOP = re.compile(r"in Loop: Header=BB(\d+_\d+) Depth=(\d+)")
+_PARENT = re.compile(r"Parent Loop BB(\d+_\d+) Depth=(\d+)")
+_DROP_LANES = re.compile(r"^\s*s_andn2_b64\s+exec,\s*exec,")
+_BARRIER = re.compile(r"^\s*s_barrier\b")
+
+
+def _functions(lines):
+    name, body = None, []
+    for line in lines:
+        m = _FUNC.match(line)
+        if m:
+            name, body = m.group(1), []
+            continue
+        if name is None:
+            continue
+        if _END.match(line):
+            yield name, body
+            name = None
+            continue
+        body.append(line)
+
+
+def _blocks(body):
+    """Split a kernel into blocks: (own loop id, annotation text, instruction lines)."""
+    blocks = []
+    for line in body:
+        lm = _LABEL.match(line)
+        if lm:
+            own = lm.group(1)[len(".LBB"):] if lm.group(1) else None
+            blocks.append([own, line, [], True])
+            continue
+        if not blocks:
+            continue
+        stripped = line.strip()
+        if stripped.startswith(";") and blocks[-1][3]:
+            blocks[-1][1] += "\n" + stripped  # annotation lines right after the label
+            continue
+        blocks[-1][3] = False
+        blocks[-1][2].append(line)
+    return [(own, note, insts) for own, note, insts, _ in blocks]
+
+
+def check_function(body):
+    """Return a list of problems (strings) for one kernel's assembly."""
+    parent = {}  # loop header -> enclosing loop header (None at depth 1)
+    rows = []    # (innermost loop of the block, holds barrier, drops lanes)
+    for own, note, insts in _blocks(body):
+        loop = None
+        if _HEADER.search(note) and own is not None:
+            loop = own
+            ps = sorted((int(d), h) for h, d in _PARENT.findall(note))
+            parent[own] = ps[-1][1] if ps else None
+            for (_, a), (_, b) in zip(ps, ps[1:]):
+                parent.setdefault(b, a)
+            if ps:
+                parent.setdefault(ps[0][1], None)
+        else:
+            im = _IN_LOOP.search(note)
+            if im:
+                loop = im.group(1)
+        rows.append((loop, any(_BARRIER.match(i) for i in insts), any(_DROP_LANES.match(i) for i in insts)))
+
+    def ancestors(h):
+        seen = []
+        while h is not None and h not in seen:
+            seen.append(h)
+            h = parent.get(h)
+        return seen
+
+    holds_barrier = set()
+    for loop, bar, _ in rows:
+        if bar and loop is not None:
+            holds_barrier.update(ancestors(loop))
+    problems = {f"loop BB{loop} holds s_barrier and has a divergent exit"
+                for loop, _, drop in rows if drop and loop in holds_barrier}
+    return sorted(problems)
+
+
+def check_file(path):
+    """Problems in every kernel of one assembly file: {kernel: [problems]}."""
+    lines = Path(path).read_text().splitlines()
+    out = {}
+    for name, body in _functions(lines):
+        p = check_function(body)
+        if p:
+            out[name] = p
+    return out
+
+
+def main(argv):
+    bad = 0
+    for path in argv:
+        for name, probs in check_file(path).items():
+            bad += 1
+            for p in probs:
+                print(f"{path}: {name}: {p}")
+    return 1 if bad else 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

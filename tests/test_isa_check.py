@@ -1,0 +1,92 @@
+"""The build's check for barriers inside loops with divergent exits.
+
+Two hand-written assembly fragments in the form hipcc emits: a work loop whose
+barrier sits in a loop that thread 0 leaves on its own (the shape that makes a
+workgroup spin), and the same work loop with only a uniform exit.
+"""
+
+import sys
+from pathlib import Path
+
+sys.path.insert(0, str(Path(__file__).resolve().parents[1] / "paper_1704_02278_amd"))
+import isa_check  # noqa: E402
+
+BAD = """\
+kern:                                   ; @kern
+	s_load_dwordx2 s[0:1], s[4:5], 0x0
+	s_branch .LBB0_2
+.LBB0_1:                                ;   in Loop: Header=BB0_2 Depth=1
+	s_or_b64 exec, exec, s[4:5]
+	s_andn2_b64 exec, exec, s[50:51]
+	s_cbranch_execz .LBB0_9
+.LBB0_2:                                ; =>This Loop Header: Depth=1
+                                        ;     Child Loop BB0_4 Depth 2
+	s_and_saveexec_b64 s[4:5], s[48:49]
+	global_atomic_add_x2 v[2:3], v37, v[2:3], s[20:21] offset:16 sc0
+.LBB0_4:                                ;   Parent Loop BB0_2 Depth=1
+                                        ; =>  This Loop Header: Depth=2
+	ds_write_b32 v65, v37
+	s_waitcnt lgkmcnt(0)
+	s_barrier
+	ds_read_b64 v[4:5], v37 offset:128
+	s_cbranch_vccnz .LBB0_5
+; %bb.3:                                ;   in Loop: Header=BB0_4 Depth=2
+	s_mov_b64 s[4:5], s[48:49]
+.LBB0_5:                                ;   in Loop: Header=BB0_4 Depth=2
+	s_and_b64 s[4:5], exec, s[4:5]
+	s_or_b64 s[60:61], s[4:5], s[60:61]
+	s_andn2_b64 exec, exec, s[60:61]
+	s_cbranch_execnz .LBB0_4
+; %bb.6:                                ;   in Loop: Header=BB0_2 Depth=1
+	s_branch .LBB0_1
+.LBB0_9:
+	s_endpgm
+.Lfunc_end0:
+"""
+
+GOOD = """\
+kern:                                   ; @kern
+	s_load_dwordx2 s[0:1], s[4:5], 0x0
+.LBB0_1:                                ; =>This Loop Header: Depth=1
+                                        ;     Child Loop BB0_3 Depth 2
+	s_waitcnt lgkmcnt(0)
+	s_barrier
+	ds_read_b64 v[4:5], v37 offset:128
+	s_cbranch_vccnz .LBB0_9
+.LBB0_3:                                ;   Parent Loop BB0_1 Depth=1
+                                        ; =>  This Inner Loop Header: Depth=2
+	global_load_dword v2, v[0:1], off
+	s_or_b64 s[6:7], vcc, s[6:7]
+	s_andn2_b64 exec, exec, s[6:7]
+	s_cbranch_execnz .LBB0_3
+; %bb.4:                                ;   in Loop: Header=BB0_1 Depth=1
+	s_or_b64 exec, exec, s[6:7]
+	s_and_saveexec_b64 s[4:5], s[48:49]
+	global_atomic_add_x2 v[2:3], v37, v[2:3], s[20:21] offset:16 sc0
+	s_or_b64 exec, exec, s[4:5]
+	s_branch .LBB0_1
+.LBB0_9:
+	s_endpgm
+.Lfunc_end0:
+"""
+
+
+def _check(text, tmp_path):
+    f = tmp_path / "k.s"
+    f.write_text(text)
+    return isa_check.check_file(f)
+
+
+def test_flags_barrier_loop_with_divergent_exit(tmp_path):
+    got = _check(BAD, tmp_path)
+    assert set(got) == {"kern"}
+    assert got["kern"] == ["loop BB0_2 holds s_barrier and has a divergent exit",
+                           "loop BB0_4 holds s_barrier and has a divergent exit"]
+
+
+def test_accepts_uniform_exit_with_divergent_inner_loop(tmp_path):
+    assert _check(GOOD, tmp_path) == {}
+
+
+def test_divergent_loop_without_barrier_is_fine(tmp_path):
+    assert _check(GOOD.replace("\ts_barrier\n", ""), tmp_path) == {}
