@@ -25,9 +25,9 @@
 //          Each tile's matched starts (offset, deepest terminal state) are
 //          staged in workspace; the tile's record count is written out.
 //          At stride 4 the walks are deferred: hit words go to a
-//          workgroup-wide LDS list, and waves take 16 listed words (64
-//          offsets) at a time between their tiles, so no wave stalls on walk
-//          latency for a single tile and the stream never pauses.
+//          workgroup-wide LDS list that all waves walk together, 16 words (64
+//          offsets) per wave at a time, once the work item's tiles have
+//          streamed, so no wave's stream stalls on walk latency.
 // emit  -- turns the per-tile record counts into output positions (sum over
 //          earlier work items, then a block scan over the tiles) and writes the
 //          (offset, id) records in order, plus the per-pattern counts.  A tile
@@ -528,9 +528,8 @@ __device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, cons
 
 // Workgroup hit list of the current work item (stride 4).
 struct HitList {
-    uint32_t *hits;     // kHitCap entries (LDS)
-    uint32_t *count;    // entries reserved, all of which get written (LDS)
-    uint32_t *claimed;  // entries taken by walkers (LDS)
+    uint32_t *hits;   // kHitCap entries (LDS)
+    uint32_t *count;  // entries reserved, all of which get written (LDS)
 };
 
 // Record tile t's hit words in the list; false if they do not fit (then the
@@ -612,29 +611,6 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
         if (slot < kStageCap) P.staging[t * kStageCap + slot] = ((uint64_t)off << 32) | last;
         atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)P.d.term[2 * last + 1]);
     }
-}
-
-// Take 16 listed hit words if that many are waiting, and walk them.
-template <bool BATCH, int TILE>
-__device__ __forceinline__ void claim_and_walk(const ScanParams &P, const HitList &L, uint64_t tb,
-                                               const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l,
-                                               uint32_t *failed) {
-    uint32_t got = 0, first = 0;
-    if (lane_id() == 0) {
-        uint32_t c = __hip_atomic_load(L.claimed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        while (c + 16u <= __hip_atomic_load(L.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-            const uint32_t prev = atomicCAS(L.claimed, c, c + 16u);
-            if (prev == c) {
-                got = 1;
-                first = c;
-                break;
-            }
-            c = prev;
-        }
-    }
-    got = __builtin_amdgcn_readfirstlane(got);
-    first = __builtin_amdgcn_readfirstlane(first);
-    if (got) walk_listed<BATCH, TILE>(P, L, first, 16u, tb, cls, nm_l, rec_l, failed);
 }
 
 // ---- stride 1: one probe per offset (or none: walk every offset) ----------
@@ -775,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
     constexpr bool kDefer = STRIDE == 4;
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t hl_count, hl_claimed, item_failed;
+    __shared__ uint32_t hl_count, item_failed;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
@@ -785,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     uint32_t *nm_l = reinterpret_cast<uint32_t *>(lds + Lo.nm_off());
     uint64_t *rec_l = reinterpret_cast<uint64_t *>(lds + Lo.rec_off());
-    const HitList HL{reinterpret_cast<uint32_t *>(lds + Lo.hits_off()), &hl_count, &hl_claimed};
+    const HitList HL{reinterpret_cast<uint32_t *>(lds + Lo.hits_off()), &hl_count};
 
     // One text: the emit kernel adds into the counts after this kernel ends.
     // (A batch's prep kernel zeroes them.)
@@ -806,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull)
                         : (uint64_t)blockIdx.x;
         item_failed = 0;
-        if (kDefer) hl_count = hl_claimed = 0;
+        if (kDefer) hl_count = 0;
     }
     reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
     for (;;) {
@@ -839,7 +815,6 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                     if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
                         walk_hits4<R>(P, t, cur, pbits, xb, cls, queue, sink);
                 }
-                claim_and_walk<BATCH, TILE>(P, HL, tb, cls, nm_l, rec_l, &item_failed);
             } else {
                 uint32_t m[R / 2];
                 tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, m);
@@ -851,8 +826,8 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         if (kDefer) {
             // The rest of the list, shared by all waves.
             __syncthreads();
-            const uint32_t n = hl_count, c0 = hl_claimed;
-            for (uint32_t f = c0 + wave * 16u; f < n; f += kWaves * 16u)
+            const uint32_t n = hl_count;
+            for (uint32_t f = wave * 16u; f < n; f += kWaves * 16u)
                 walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, cls, nm_l, rec_l, &item_failed);
         }
         __syncthreads();
@@ -869,7 +844,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             P.itemsum[item] = item_failed ? kItemFailed : part;
             item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull) : ~0ull;
             item_failed = 0;
-            if (kDefer) hl_count = hl_claimed = 0;
+            if (kDefer) hl_count = 0;
         }
         reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
     }
