@@ -97,6 +97,18 @@ def cpu_threads() -> int:
     return max(1, min(16, n))
 
 
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": cpu_threads(), "model": model}
+
+
 def cpu_baseline(text: np.ndarray, pats, target_s: float) -> dict:
     import oracle
 
@@ -110,7 +122,7 @@ def cpu_baseline(text: np.ndarray, pats, target_s: float) -> dict:
     t0 = time.perf_counter()
     _, _, _, total = oracle.match(text[:n], pats, bucketed=True, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(n / dt / 1e9, 6), "unit": "GB/s", "cores": threads, "kind": "oracle",
+    return {"value": round(n / dt / 1e9, 6), "unit": "GB/s", "cores": threads, "kind": "oracle", "host": host_info(),
             "sample": f"first {n / 2**20:.0f} MiB of the same text, bucketed memcmp oracle, {threads} threads, "
                       f"{dt:.1f} s, {total} matches"}
 
@@ -131,15 +143,141 @@ def cpu_trie_baseline(d, text: np.ndarray, target_s: float) -> dict:
     return {"kind": "failureless-trie walk on the host (the paper's CPU counterpart)", **out}
 
 
+def bench_batched(reps: int) -> dict:
+    """Many independent texts: one batched call (graph replay) vs one plain call per text.
+
+    Plain is timed twice: the per-chunk glop_match_ws calls issued from Python
+    (eager) and the same calls captured once in a graph and replayed (no host
+    launch cost).  Both write every chunk's records; the batched result must
+    equal them chunk by chunk (checked outside the timed regions).
+    """
+    import torch
+
+    import paper_1704_02278_amd as glop
+    import synth
+
+    t0 = time.perf_counter()
+    pats, text, offs, sizes, plants = synth.make_chunks("batched")
+    nchunks, nbytes = len(sizes), int(text.size)
+    log(f"[bench] batched: {nchunks} chunks, {nbytes} bytes, generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    buf = torch.from_numpy(text).to(dev)
+    del text
+    chunks = [buf[o:o + n] for o, n in zip(offs.tolist(), sizes)]
+    d = glop.Dict(pats)
+    npat = len(pats)
+    stream = torch.cuda.current_stream()
+
+    # Plain: one glop_match_ws per chunk into its own slice of one output buffer.
+    caps = [16 + n // 2048 for n in sizes]
+    bases = np.zeros(nchunks + 1, dtype=np.int64)
+    bases[1:] = np.cumsum(caps)
+    out_plain = torch.zeros((int(bases[-1]), 2), dtype=torch.int64, device=dev)
+    totals = torch.zeros(nchunks, dtype=torch.int64, device=dev)
+    counts_plain = torch.empty(npat, dtype=torch.int64, device=dev)
+    ws_bytes = d.workspace_bytes(max(sizes))
+    ws_buf = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    ws = ws_buf[(-ws_buf.data_ptr()) % 256:][:ws_bytes]
+    outs = [out_plain[int(bases[k]):int(bases[k + 1])] for k in range(nchunks)]
+    tots = [totals[k:k + 1] for k in range(nchunks)]
+
+    def plain_all():
+        for k in range(nchunks):
+            d.match_into(chunks[k], outs[k], counts_plain, total=tots[k], workspace=ws, stream=stream)
+
+    # Batched: one glop_match_batch over the chunk table.
+    table = torch.tensor([[c.data_ptr(), c.numel()] for c in chunks], dtype=torch.int64).to(dev)
+    cap_b = int(bases[-1])
+    out_b = torch.zeros((cap_b, 2), dtype=torch.int64, device=dev)
+    first = torch.empty(nchunks, dtype=torch.int64, device=dev)
+    count = torch.empty(nchunks, dtype=torch.int64, device=dev)
+    counts_b = torch.empty(npat, dtype=torch.int64, device=dev)
+    total_b = torch.zeros(1, dtype=torch.int64, device=dev)
+    wsb_bytes = d.batch_workspace_bytes(nchunks, nbytes)
+    wsb_buf = torch.empty(wsb_bytes + 256, dtype=torch.uint8, device=dev)
+    wsb = wsb_buf[(-wsb_buf.data_ptr()) % 256:][:wsb_bytes]
+
+    def batched():
+        d.match_batch_into(table, nchunks, nbytes, out_b, first, count, counts_b, total_b, wsb, stream=stream)
+
+    def timed(fn, n):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(n):
+            torch.cuda.synchronize()
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return np.array(ms)
+
+    # Warm-up, then capture both forms as graphs (the capture stream is torch's).
+    plain_all()
+    batched()
+    torch.cuda.synchronize()
+    g_plain, g_batch = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g_plain, stream=cs):
+            for k in range(nchunks):
+                d.match_into(chunks[k], outs[k], counts_plain, total=tots[k], workspace=ws, stream=cs)
+        with torch.cuda.graph(g_batch, stream=cs):
+            d.match_batch_into(table, nchunks, nbytes, out_b, first, count, counts_b, total_b, wsb, stream=cs)
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+
+    t_eager = timed(plain_all, max(2, reps // 5))
+    t_plain_graph = timed(g_plain.replay, reps)
+    t_batch_graph = timed(g_batch.replay, reps)
+    t_batch_eager = timed(batched, reps)
+
+    # Same records chunk by chunk (plain slices vs batched segments), same totals.
+    tb = int(total_b.item())
+    assert 0 <= tb <= cap_b, tb
+    tot = totals.cpu().numpy()
+    fst, cnt = first.cpu().numpy(), count.cpu().numpy()
+    assert np.array_equal(cnt, tot) and tb == int(tot.sum())
+    assert all(len(p) <= t for p, t in zip(plants, tot.tolist()))
+    ob, op = out_b[:tb].cpu().numpy(), out_plain.cpu().numpy()
+    idx_plain = np.concatenate([np.arange(bases[k], bases[k] + tot[k]) for k in range(nchunks)])
+    assert np.array_equal(ob[:, 0], op[idx_plain, 0])
+    assert np.array_equal(ob[:, 1] & 0xFFFFFFFF, op[idx_plain, 1])
+    assert np.array_equal(ob[:, 1] >> 32, np.repeat(np.arange(nchunks), tot))
+    assert np.array_equal(fst, np.concatenate([[0], np.cumsum(tot)[:-1]]))
+
+    def rate(ms):
+        return round(nbytes / (float(np.median(ms)) / 1e3) / 1e9, 2)
+
+    return {
+        "workload": "4,096 independent log texts (lognormal sizes, median 256 KiB, sigma 2.16, 1 KiB-64 MiB), "
+                    "1,000-pattern dictionary",
+        "chunks": nchunks, "bytes": nbytes, "matches": tb, "reps": reps,
+        "batched_graph": {"ms_median": round(float(np.median(t_batch_graph)), 4),
+                          "ms_min": round(float(t_batch_graph.min()), 4), "GBps": rate(t_batch_graph),
+                          "hbm_frac": round(rate(t_batch_graph) / HBM_PEAK_GBS, 4)},
+        "batched_eager": {"ms_median": round(float(np.median(t_batch_eager)), 4), "GBps": rate(t_batch_eager)},
+        "plain_graph": {"ms_median": round(float(np.median(t_plain_graph)), 4), "GBps": rate(t_plain_graph),
+                        "launches": 2 * nchunks},
+        "plain_eager": {"ms_median": round(float(np.median(t_eager)), 4), "GBps": rate(t_eager)},
+        "speedup_vs_plain_graph": round(float(np.median(t_plain_graph) / np.median(t_batch_graph)), 2),
+        "speedup_vs_plain_eager": round(float(np.median(t_eager) / np.median(t_batch_graph)), 2),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOAD_LABEL))
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy of the text")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (many texts) comparison")
+    ap.add_argument("--batched-reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the matcher has no multi-GPU path "
@@ -214,6 +352,21 @@ def main() -> int:
     achieved = scan_bytes / (scan_avg / 1e3) / 1e9
     value = n / (ms_per_step / 1e3) / 1e9
 
+    # Read-stream ceiling of this device, same session: one read of the text.
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    assert t_dev.data_ptr() % 16 == 0
+    for _ in range(3):
+        glop.stream_read(t_dev, sink, stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(20):
+        glop.stream_read(t_dev, sink, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    read_ms = a.elapsed_time(b) / 20
+    read_gbs = (n - n % 16) / (read_ms / 1e3) / 1e9
+
     copy = None
     if args.copy_probe:
         dst = torch.empty_like(t_dev)
@@ -248,6 +401,7 @@ def main() -> int:
                    "form": "plain (one glop_match_ws call per step)"},
         "gbps_eq1": round(8 * value, 2),
         "hbm_frac": round(value / HBM_PEAK_GBS, 5),
+        "step_ms_mean": round(float(step_ms.mean()), 5),
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "matches": got_total,
@@ -255,6 +409,9 @@ def main() -> int:
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.workload),
                      "kernel": "glop_scan_kernel", "kernel_ms_avg": round(scan_avg, 5),
                      "algorithmic_bytes_per_launch": int(scan_bytes)},
+        "read_stream_ceiling": {"GBps": round(read_gbs, 1), "ms": round(read_ms, 5),
+                                "value_frac": round(value / read_gbs, 4), "scan_frac": round(achieved / read_gbs, 4),
+                                "kernel": "glop_stream_read_kernel (same load shape as the scan)"},
         "dictionary": {k: info[k] for k in ("num_states", "num_classes", "stride", "qgram", "bitmap_log2",
                                             "filter_keys", "table_bytes")},
         "paper_context": "20 Gbps (2.5 GB/s) PFAC texture-memory kernel on a Tesla K20m, 100 MB logs, "
@@ -262,6 +419,11 @@ def main() -> int:
     }
     if copy:
         result["copy_probe"] = copy
+    if not args.no_batched and args.workload == "medium":
+        del out, ws_buf, t_dev
+        torch.cuda.empty_cache()
+        log("[bench] batched comparison ...")
+        result["batched"] = bench_batched(args.batched_reps)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(text, pats, args.cpu_seconds)

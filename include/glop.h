@@ -274,6 +274,29 @@ typedef struct {
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 
+/* Number of patterns and the longest pattern length of a dictionary (0 for a
+ * null handle).  The longest length minus one is the overlap that a caller
+ * splitting one text into independent pieces must give each piece (Section 4:
+ * consecutive chunks share that many bytes so that no occurrence is cut). */
+uint32_t glop_num_patterns(glop_handle_t h);
+uint32_t glop_max_len(glop_handle_t h);
+
+/* ---- Measurement helper -----------------------------------------------------
+ *
+ * glop_stream_read: read the first floor(len / 16) * 16 bytes at d_data once,
+ * with the same 16-byte-per-lane coalesced loads as the scan kernel, and fold
+ * them into the device uint64_t at d_sink (its value afterwards depends on
+ * every byte read and is otherwise unspecified).  Its rate is
+ * the practical ceiling for a pure HBM read stream on this device, against
+ * which the matcher's rate is reported (Eq. 1 counts text bytes per second).
+ *   d_data  device pointer, 16-byte aligned; not modified.
+ *   d_sink  device pointer to one uint64_t.
+ *   stream  hipStream_t or NULL (the null stream); the call is asynchronous.
+ * Errors: GLOP_EINVAL (null or misaligned pointer with len >= 16),
+ *         GLOP_EHIP (launch failure).
+ */
+int glop_stream_read(const uint8_t *d_data, uint64_t len, uint64_t *d_sink, void *stream);
+
 int glop_last_error(void);
 const char *glop_last_error_message(void);
 const char *glop_strerror(int code);

@@ -90,6 +90,9 @@ _SIGNATURES = {
                                         _vp]),
     "glop_cpu_walk": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_int]),
     "glop_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(glop_info_t)]),
+    "glop_num_patterns": (ctypes.c_uint32, [_vp]),
+    "glop_max_len": (ctypes.c_uint32, [_vp]),
+    "glop_stream_read": (ctypes.c_int, [_vp, _u64, _vp, _vp]),
     "glop_last_error": (ctypes.c_int, []),
     "glop_last_error_message": (ctypes.c_char_p, []),
     "glop_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -139,7 +142,8 @@ class Dict:
         if not h:
             raise GlopError(glop_last_error(), "glop_build_ex" if device else "glop_compile")
         self._h = ctypes.c_void_p(h)
-        self.num_patterns = n
+        self.num_patterns = int(glop_num_patterns(self._h))
+        self.max_len = int(glop_max_len(self._h))
         self.pattern_lengths = [len(p) for p in patterns]
         del keep
 
@@ -299,3 +303,12 @@ class Dict:
 
 def build(patterns, **opts) -> Dict:
     return Dict(patterns, **opts)
+
+
+def stream_read(data, sink, stream=None):
+    """Enqueue one read of a 16-byte aligned uint8 CUDA tensor (the HBM read
+    ceiling the matcher is compared with); ``sink`` is an int64 CUDA tensor [1]."""
+    import torch
+
+    s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    _check(glop_stream_read(data.data_ptr(), int(data.numel()), sink.data_ptr(), s), "glop_stream_read")

@@ -42,6 +42,13 @@ int hip_fail(hipError_t e, const char *what) {
 
 constexpr uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
+hipError_t num_cus(int *cus) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
 std::mutex g_prep_mu;
 bool g_prepared[64] = {};
 
@@ -310,6 +317,22 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->filter_keys = c.filter_keys;
     out->device_bytes = h->blob_bytes;
     out->device = h->blob ? h->device : -1;
+    return ok();
+}
+
+uint32_t glop_num_patterns(glop_handle_t h) { return h ? h->c.num_patterns : 0u; }
+
+uint32_t glop_max_len(glop_handle_t h) { return h ? h->c.max_len : 0u; }
+
+int glop_stream_read(const uint8_t *d_data, uint64_t len, uint64_t *d_sink, void *stream) {
+    if (!d_sink) return fail(GLOP_EINVAL, "NULL sink");
+    if (len >= 16 && (!d_data || (reinterpret_cast<uintptr_t>(d_data) & 15u)))
+        return fail(GLOP_EINVAL, "data must be a 16-byte aligned device pointer");
+    int cus = 0;
+    hipError_t e = num_cus(&cus);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    e = glop::launch_stream_read(d_data, len, d_sink, cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return ok();
 }
 

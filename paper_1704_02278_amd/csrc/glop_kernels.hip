@@ -37,6 +37,28 @@ const VariantFns &variant_for(const GlopDevDict &d) {
     return q4 ? GLOP_VARIANT_ID(1, 1, 1, 1, 8)() : GLOP_VARIANT_ID(1, 1, 1, 0, 8)();
 }
 
+// Read stream with the scan kernel's load shape: each wave takes 8 KiB tiles,
+// a lane loads 16 bytes per 1 KiB round, all eight rounds in flight at once.
+__global__ __launch_bounds__(kBlock) void glop_stream_read_kernel(const uint4 *p, uint64_t n16, uint64_t *sink) {
+    constexpr uint32_t kTile16 = 8 * kWave;  // 16-byte units per 8 KiB tile
+    const uint64_t waves = (uint64_t)gridDim.x * kWaves;
+    uint32_t acc = 0;
+    for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave_id(); tile * kTile16 < n16; tile += waves) {
+        const uint64_t base = tile * kTile16 + lane_id();
+        uint4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t i = base + (uint64_t)k * kWave;
+            v[k] = i < n16 ? p[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o);
+    if (lane_id() == 0) atomicXor(reinterpret_cast<unsigned int *>(sink), acc);
+}
+
 ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
     ScanParams P{};
     P.d = d;
@@ -118,6 +140,13 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.meta = reinterpret_cast<uint64_t *>(ws + g.off_meta);
     const EmitParams E{reinterpret_cast<glop_match_t *>(a.out), a.max_matches, nullptr, a.chunk_first};
     return variant_for(d).batch(P, E, a.chunk_count, a.total, a.num_cus, stream);
+}
+
+hipError_t launch_stream_read(const uint8_t *data, uint64_t len, uint64_t *sink, int num_cus, hipStream_t stream) {
+    const uint32_t grid = 2u * (uint32_t)(num_cus > 0 ? num_cus : 1);  // two 1024-thread groups per CU
+    hipLaunchKernelGGL(glop_stream_read_kernel, dim3(grid), dim3(kBlock), 0, stream,
+                       reinterpret_cast<const uint4 *>(data), len / 16, sink);
+    return hipGetLastError();
 }
 
 }  // namespace glop

@@ -52,4 +52,8 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream);
 // One-time per-device kernel attribute setup (dynamic LDS above 64 KiB).
 hipError_t prepare_kernels();
 
+// Read floor(len / 16) * 16 bytes once (16-byte aligned data) and fold them
+// into *sink: the HBM read-stream ceiling the scan kernel is compared with.
+hipError_t launch_stream_read(const uint8_t *data, uint64_t len, uint64_t *sink, int num_cus, hipStream_t stream);
+
 }  // namespace glop

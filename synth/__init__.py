@@ -14,6 +14,9 @@ generators stand in for them with the shapes of the workloads studied here:
   1 plant / 64 KiB
 * ``large``  -- 20,000 patterns, Zipf(1.2) lengths on 4-128 B, 40 % shared
   prefixes, over 4 GiB, 1 plant / 16 KiB
+* ``batched`` (``make_chunks``) -- the medium dictionary over 4,096 independent
+  texts whose sizes are lognormal (median 256 KiB, sigma 2.16) clipped to
+  [1 KiB, 64 MiB], about 8 GiB in all, 1 plant / 64 KiB in each
 
 Every random draw comes from MT19937-64 substreams (``synth.c``) selected by
 (seed, stream, block), so the output does not depend on thread counts.
@@ -40,6 +43,9 @@ BASE_SEED = 170402278
 STREAM_PATTERNS = 1 << 20
 STREAM_TEXT = 2 << 20
 STREAM_PLANTS = 3 << 20
+# Chunked workloads: sizes, then (text, plants) per chunk.
+STREAM_CHUNK_SIZES = 4 << 20
+STREAM_CHUNKS = 5 << 20
 
 
 def build_library(force: bool = False) -> Path:
@@ -263,12 +269,13 @@ _NL_MARGIN = 512
 
 
 def plant(text: np.ndarray, patterns: list[bytes], every: int, seed: int = BASE_SEED,
-          stream_id: int = STREAM_PLANTS) -> list[tuple[int, int]]:
+          stream_id: int = STREAM_PLANTS, draw_chunk: int = 1 << 16) -> list[tuple[int, int]]:
     """Overwrite ``text`` with one occurrence per ``every``-byte slot.
 
     Each plant picks a pattern uniformly, lies wholly inside its slot (so plants
     never overlap) and inside one line (it never covers a newline).  Returns the
-    sorted list of (offset, pattern id) planted.
+    sorted list of (offset, pattern id) planted.  ``draw_chunk`` only sizes the
+    draw buffer (the draws themselves do not depend on it).
     """
     if every <= 0 or not patterns:
         return []
@@ -276,7 +283,7 @@ def plant(text: np.ndarray, patterns: list[bytes], every: int, seed: int = BASE_
     nslots = n // every
     if nslots == 0:
         return []
-    d = Draws(seed, stream_id)
+    d = Draws(seed, stream_id, chunk=draw_chunk)
     plants = []
     for m in range(nslots):
         lo, hi = m * every, (m + 1) * every
@@ -335,3 +342,60 @@ def make_workload(name: str, seed: int = BASE_SEED, n_bytes: int | None = None,
     text = gen_text(tspec, seed, STREAM_TEXT + w.index, threads=threads)
     plants = plant(text, pats, tspec.plant_every, seed, STREAM_PLANTS + w.index)
     return pats, text, plants
+
+
+@dataclasses.dataclass(frozen=True)
+class ChunkSpec:
+    count: int
+    median: int
+    sigma: float
+    size_min: int
+    size_max: int
+    plant_every: int
+
+
+CHUNKED = {
+    # Many independent texts matched as one batch, against the medium dictionary.
+    "batched": ("medium", ChunkSpec(count=4096, median=256 << 10, sigma=2.16, size_min=1 << 10,
+                                    size_max=64 << 20, plant_every=64 << 10)),
+}
+
+
+def chunk_sizes(spec: ChunkSpec, seed: int = BASE_SEED, stream_id: int = STREAM_CHUNK_SIZES) -> list[int]:
+    """Lognormal sizes (Box-Muller normals from one substream), clipped."""
+    d = Draws(seed, stream_id)
+    out = []
+    mu = np.log(spec.median)
+    for _ in range(spec.count):
+        u1 = 1.0 - d.unit()  # (0, 1]
+        u2 = d.unit()
+        z = float(np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
+        size = int(round(float(np.exp(mu + spec.sigma * z))))
+        out.append(min(max(size, spec.size_min), spec.size_max))
+    return out
+
+
+def make_chunks(name: str = "batched", seed: int = BASE_SEED, count: int | None = None,
+                threads: int | None = None):
+    """(patterns, text, offsets, sizes, plants): chunk k is text[offsets[k]:offsets[k]+sizes[k]],
+    generated and planted on its own; ``plants[k]`` lists its (offset in chunk, id).
+    ``count`` keeps only the first chunks (smaller test cases of the same draw)."""
+    dict_name, spec = CHUNKED[name]
+    w = WORKLOADS[dict_name]
+    pats = gen_patterns(w.patterns, seed, STREAM_PATTERNS + w.index)
+    sizes = chunk_sizes(spec, seed)
+    if count is not None:
+        sizes = sizes[:count]
+    offsets = np.zeros(len(sizes), dtype=np.int64)
+    if sizes:
+        offsets[1:] = np.cumsum(sizes[:-1])
+    text = np.empty(int(sum(sizes)), dtype=np.uint8)
+    plants = []
+    for k, (o, n) in enumerate(zip(offsets.tolist(), sizes)):
+        view = text[o:o + n]
+        tspec = dataclasses.replace(w.text, n_bytes=n, plant_every=spec.plant_every)
+        gen_text(tspec, seed, STREAM_CHUNKS + 2 * k, threads=threads, out=view)
+        plants.append(plant(view, pats, spec.plant_every, seed, STREAM_CHUNKS + 2 * k + 1,
+                            draw_chunk=64 + 4 * (n // spec.plant_every)))
+    return pats, text, offsets, sizes, plants
+

@@ -118,3 +118,14 @@ def test_workspace_grows_with_length():
     d = host_dict([b"abc"])
     a, b = d.workspace_bytes(1 << 20), d.workspace_bytes(1 << 30)
     assert 0 < a < b and b % 256 == 0
+
+
+def test_size_getters_and_stream_probe_argument_checks():
+    d = host_dict([b"abc", b"de", b"fghij"])
+    assert glop.glop_num_patterns(d.handle) == 3 == d.num_patterns
+    assert glop.glop_max_len(d.handle) == 5 == d.max_len
+    assert glop.glop_num_patterns(None) == 0 and glop.glop_max_len(None) == 0
+    # Rejected before any device work: no sink, or data that is not 16-byte aligned.
+    assert glop.glop_stream_read(None, 0, None, None) == glop.GLOP_EINVAL
+    assert glop.glop_stream_read(17, 64, 4096, None) == glop.GLOP_EINVAL
+    assert glop.glop_stream_read(None, 16, 4096, None) == glop.GLOP_EINVAL

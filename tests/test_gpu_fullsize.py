@@ -7,6 +7,11 @@
   (every record is a true occurrence, ascending and unique, counts add up,
   every planted occurrence is reported) and 128 sampled windows are compared
   record by record with the oracle run on each window plus its halo.
+* batched (4,096 independent texts, about 7.7 GiB, medium dictionary) through
+  glop_match_batch: every chunk's records, its position and record count, and
+  the batch's per-pattern counts, against one oracle run over the chunks laid
+  end to end, keeping the occurrences that lie wholly inside one chunk (the
+  union of the per-chunk results, since the oracle is the plain definition).
 """
 
 import numpy as np
@@ -18,6 +23,7 @@ import synth
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 glop = pytest.importorskip("paper_1704_02278_amd")
+from chunks import split_by_chunk  # noqa: E402
 from gpu_util import assert_same, gpu_match, oracle_match, say, to_device  # noqa: E402
 
 
@@ -58,3 +64,34 @@ def test_large_full_size_properties_and_sampled_windows():
         w_ids = o_ids[keep].astype(np.uint64)
         a, b = np.searchsorted(off, lo), np.searchsorted(off, hi)
         assert np.array_equal(off[a:b], w_off) and np.array_equal(ids[a:b], w_ids), f"window at {lo}"
+
+
+def test_batched_full_size_bit_exact():
+    import torch
+
+    pats, text, offs, sizes, plants = synth.make_chunks("batched")
+    say("fullsize batched", len(sizes), text.size)
+    buf = torch.from_numpy(text).to("cuda")
+    chunks = [buf[o:o + n] for o, n in zip(offs.tolist(), sizes)]
+    d = glop.Dict(pats)
+    g_off, g_ids, g_cid, first, count, counts, total = d.match_batch(chunks)
+    g_off, g_ids, g_cid = (x.cpu().numpy().astype(np.uint64) for x in (g_off, g_ids, g_cid))
+    first, count = first.cpu().numpy(), count.cpu().numpy()
+    counts = counts.cpu().numpy().astype(np.uint64)
+    del buf, chunks
+
+    say("fullsize batched: oracle over the concatenation")
+    w_off, w_ids, _, _ = oracle_match(text, pats)
+    k, w_rel, w_ids = split_by_chunk(w_off, w_ids, [len(p) for p in pats], offs, sizes)
+    w_rel = w_rel.astype(np.uint64)
+    per_chunk = np.bincount(k, minlength=len(sizes))
+
+    assert total == w_rel.size
+    assert np.array_equal(count, per_chunk)
+    assert np.array_equal(first, np.concatenate([[0], np.cumsum(per_chunk)[:-1]]))
+    assert np.array_equal(g_cid, k.astype(np.uint64))
+    assert np.array_equal(g_off, w_rel)
+    assert np.array_equal(g_ids, w_ids.astype(np.uint64))
+    assert np.array_equal(counts, np.bincount(w_ids.astype(np.int64), minlength=len(pats)).astype(np.uint64))
+    assert all(len(p) <= c for p, c in zip(plants, per_chunk.tolist()))
+

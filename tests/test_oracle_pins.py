@@ -91,3 +91,25 @@ def test_pins_catch_planted_mistake(mutant, tmp_path):
     mut_src.write_text(text.replace(old, new))
     lib = oracle._bind(oracle.compile_oracle(mut_src, tmp_path / "libmutant.so"))
     assert pin_failures(lib, n_random=60) != [], f"no pin detects mutant {mutant}"
+
+
+def test_concatenated_oracle_split_equals_per_chunk_oracle():
+    """The batched tests' reference: one oracle run over chunks laid end to end,
+    split by chunk, equals the oracle run on each chunk alone."""
+    from chunks import split_by_chunk
+
+    pats, text, offs, sizes, _ = synth.make_chunks(count=24)
+    off, ids, _, _ = oracle.match(text, pats, bucketed=True)
+    k, rel, kid = split_by_chunk(off, ids, [len(p) for p in pats], offs, sizes)
+    for c, (o, n) in enumerate(zip(offs.tolist(), sizes)):
+        w_off, w_ids, _, w_total = oracle.match(text[o:o + n], pats, bucketed=True)
+        sel = k == c
+        assert np.array_equal(rel[sel], w_off.astype(np.int64)) and np.array_equal(kid[sel], w_ids.astype(np.int64))
+    # An occurrence that crosses a chunk boundary is found in the concatenation and dropped.
+    text = np.frombuffer(b"abcab" + b"cabc" + b"c", dtype=np.uint8)
+    pats = [b"ca", b"bc", b"c"]
+    off, ids, _, _ = oracle.match(text, pats, bucketed=False)
+    k, rel, kid = split_by_chunk(off, ids, [len(p) for p in pats], [0, 5, 9], [5, 4, 1])
+    got = list(zip(k.tolist(), rel.tolist(), kid.tolist()))
+    assert got == [(0, 1, 1), (0, 2, 0), (0, 2, 2), (1, 0, 0), (1, 0, 2), (1, 2, 1), (1, 3, 2), (2, 0, 2)]
+    assert (4, 1) in set(zip(off.tolist(), ids.tolist()))  # "bc" across the first boundary

@@ -71,3 +71,27 @@ def test_plants_are_inside_lines_and_slots():
         assert 0x0A not in p or True
         assert o // every == (o + len(p) - 1) // every
         assert 0x0A not in bytes(text[o:o + len(p)])
+
+
+def test_draw_buffer_size_does_not_change_draws():
+    a = synth.Draws(7, 11, chunk=3)
+    b = synth.Draws(7, 11)
+    assert [a.u32() for _ in range(1000)] == [b.u32() for _ in range(1000)]
+
+
+def test_chunked_workload_shape():
+    spec = synth.CHUNKED["batched"][1]
+    sizes = synth.chunk_sizes(spec)
+    assert len(sizes) == 4096 and min(sizes) >= 1 << 10 and max(sizes) <= 64 << 20
+    med = sorted(sizes)[2048]
+    assert 200 << 10 < med < 330 << 10  # lognormal median 256 KiB
+    pats, text, offs, sz, plants = synth.make_chunks(count=40)
+    assert sz == sizes[:40] and text.size == sum(sz)
+    assert pats == synth.gen_patterns(synth.WORKLOADS["medium"].patterns, synth.BASE_SEED,
+                                      synth.STREAM_PATTERNS + synth.WORKLOADS["medium"].index)
+    for k in range(40):
+        chunk = text[offs[k]:offs[k] + sz[k]]
+        assert len(plants[k]) == sz[k] // spec.plant_every
+        for o, j in plants[k]:
+            assert chunk[o:o + len(pats[j])].tobytes() == pats[j]
+        assert chunk[-1] == 0x0A  # every chunk ends a line
