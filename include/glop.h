@@ -47,6 +47,7 @@ extern "C" {
 #define GLOP_EHIP (-3)     /* a HIP runtime call failed (message names it) */
 #define GLOP_ETOOLONG (-4) /* a pattern is longer than GLOP_MAX_PATTERN_LEN */
 #define GLOP_ENODEV (-5)   /* no usable GPU, or the handle has no device copy */
+#define GLOP_EINTERNAL (-6) /* an internal consistency check failed */
 
 #define GLOP_MAX_PATTERN_LEN 65535u
 #define GLOP_MAX_PATTERNS (1u << 24)
@@ -280,6 +281,46 @@ int glop_get_info(glop_handle_t h, glop_info_t *out);
  * consecutive chunks share that many bytes so that no occurrence is cut). */
 uint32_t glop_num_patterns(glop_handle_t h);
 uint32_t glop_max_len(glop_handle_t h);
+
+/* ---- Autotuning ---------------------------------------------------------------
+ *
+ * glop_autotune: choose build options for a dictionary by timing them on a
+ * device sample of representative text.  The filter of Sections 2 and 5
+ * (prefilter, then full comparison) has free parameters the paper fixes for
+ * its own hardware; here they are measured.  Starting from the automatic
+ * options, one parameter at a time is varied (filter on or off, q-gram
+ * length, stride, probe bits, bitmap size, tile size) and a change is kept
+ * when it is at least 1 % faster (median of 7 timed calls after 2 warm-up
+ * calls).  Every option set is exact, so all of them must report the same
+ * number of matches on the sample; a difference fails the call.  The trie is
+ * built and uploaded once; candidates differ only in their filter tables.
+ *
+ * Results are cached per device architecture and compute-unit count,
+ * dictionary statistics (pattern count, shortest and longest length, trie
+ * states rounded up to a power of two) and sample size (rounded up to a power
+ * of two): in memory for the process, and in the text file named by the
+ * environment variable GLOP_TUNE_CACHE if it is set (read once, appended).
+ *
+ *   patterns, lengths, n   as for glop_build.
+ *   d_sample, sample_len   device text to time on (any alignment); at least
+ *                          1 byte.  64 MiB or more gives stable timings.
+ *   stream                 hipStream_t or NULL; the call synchronizes it.
+ *   out                    receives the chosen options (pass out->opts to
+ *                          glop_build_ex), their time and that of the
+ *                          automatic options on the sample.
+ * Errors: GLOP_EINVAL, GLOP_ETOOLONG, GLOP_ENOMEM, GLOP_EHIP, GLOP_ENODEV,
+ *         GLOP_EINTERNAL (two option sets gave different match counts).
+ */
+typedef struct {
+    glop_build_opts opts; /* chosen options (all fields explicit) */
+    float ms;             /* median time of one match of the sample with them */
+    float auto_ms;        /* the same with the automatic options */
+    uint32_t evaluated;   /* option sets timed (0 when taken from the cache) */
+    uint32_t from_cache;  /* 1 if the result came from the cache */
+} glop_tune_result_t;
+
+int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n, const uint8_t *d_sample,
+                  uint64_t sample_len, void *stream, glop_tune_result_t *out);
 
 /* ---- Measurement helper -----------------------------------------------------
  *

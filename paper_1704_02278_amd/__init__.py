@@ -31,6 +31,7 @@ GLOP_ENOMEM = -2
 GLOP_EHIP = -3
 GLOP_ETOOLONG = -4
 GLOP_ENODEV = -5
+GLOP_EINTERNAL = -6
 GLOP_FILTER_AUTO = 0
 GLOP_FILTER_NONE = 1
 GLOP_FILTER_QGRAM = 2
@@ -57,6 +58,11 @@ class glop_batch_match_t(ctypes.Structure):
 
 class glop_events_t(ctypes.Structure):
     _fields_ = [("scan_begin", ctypes.c_void_p), ("scan_end", ctypes.c_void_p), ("emit_end", ctypes.c_void_p)]
+
+
+class glop_tune_result_t(ctypes.Structure):
+    _fields_ = [("opts", glop_build_opts), ("ms", ctypes.c_float), ("auto_ms", ctypes.c_float),
+                ("evaluated", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
 
 
 class glop_info_t(ctypes.Structure):
@@ -93,6 +99,8 @@ _SIGNATURES = {
     "glop_num_patterns": (ctypes.c_uint32, [_vp]),
     "glop_max_len": (ctypes.c_uint32, [_vp]),
     "glop_stream_read": (ctypes.c_int, [_vp, _u64, _vp, _vp]),
+    "glop_autotune": (ctypes.c_int, [_u8pp, _u32p, ctypes.c_uint32, _vp, _u64, _vp,
+                                     ctypes.POINTER(glop_tune_result_t)]),
     "glop_last_error": (ctypes.c_int, []),
     "glop_last_error_message": (ctypes.c_char_p, []),
     "glop_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -312,3 +320,24 @@ def stream_read(data, sink, stream=None):
 
     s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
     _check(glop_stream_read(data.data_ptr(), int(data.numel()), sink.data_ptr(), s), "glop_stream_read")
+
+
+def autotune(patterns, sample, stream=None) -> dict:
+    """Time build options for ``patterns`` on ``sample`` (a uint8 CUDA tensor of
+    representative text) and return the fastest: {"opts": {...}, "ms",
+    "auto_ms", "evaluated", "from_cache"}.  ``Dict(patterns, **r["opts"])``
+    builds with them."""
+    import torch
+
+    keep, ptrs, lens, n = _pattern_arrays(patterns)
+    s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    r = glop_tune_result_t()
+    _check(glop_autotune(ctypes.cast(ptrs, _u8pp), lens, n, sample.data_ptr(), int(sample.numel()), s,
+                         ctypes.byref(r)), "glop_autotune")
+    del keep
+    o = r.opts
+    return {"opts": {"filter": o.filter, "stride": o.stride, "qgram": o.qgram, "bitmap_log2": o.bitmap_log2,
+                     "probe_bits": o.probe_bits, "tile_kib": o.tile_kib},
+            "ms": float(r.ms), "auto_ms": float(r.auto_ms), "evaluated": int(r.evaluated),
+            "from_cache": bool(r.from_cache)}
+

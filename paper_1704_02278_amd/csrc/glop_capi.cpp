@@ -1,7 +1,11 @@
 // C-ABI of the matcher: argument checks, dictionary upload, workspace, errors.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -166,9 +170,288 @@ int check_match_args(const glop_dict *h, const uint8_t *text, uint64_t len, cons
     return GLOP_OK;
 }
 
+// ---- Autotuning --------------------------------------------------------------
+
+uint32_t ceil_log2_u64(uint64_t v) {
+    uint32_t k = 0;
+    while (k < 63 && (1ull << k) < v) ++k;
+    return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, glop_tune_result_t> g_tune_cache;
+bool g_tune_file_read = false;
+
+std::string tune_key(const glop_dict *h, uint64_t sample_len) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    const glop::Compiled &c = h->c;
+    char buf[320];
+    std::snprintf(buf, sizeof buf, "%s|cu%d|n%u|min%u|max%u|states2^%u|sample2^%u", arch.c_str(), h->num_cus,
+                  c.num_patterns, c.min_len, c.max_len, ceil_log2_u64(c.num_states), ceil_log2_u64(sample_len));
+    return buf;
+}
+
+// Cache file lines: key TAB filter stride qgram bitmap_log2 probe_bits tile_kib ms auto_ms
+void tune_file_read_locked() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = std::getenv("GLOP_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        glop_tune_result_t r{};
+        int filter = 0;
+        unsigned stride = 0, qgram = 0, lg = 0, pb = 0, tile = 0;
+        if (std::sscanf(tab + 1, "%d %u %u %u %u %u %f %f", &filter, &stride, &qgram, &lg, &pb, &tile, &r.ms,
+                        &r.auto_ms) != 8)
+            continue;
+        r.opts.filter = filter;
+        r.opts.stride = stride;
+        r.opts.qgram = qgram;
+        r.opts.bitmap_log2 = lg;
+        r.opts.probe_bits = pb;
+        r.opts.tile_kib = tile;
+        g_tune_cache[line] = r;
+    }
+    std::fclose(f);
+}
+
+void tune_file_append_locked(const std::string &key, const glop_tune_result_t &r) {
+    const char *path = std::getenv("GLOP_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%d %u %u %u %u %u %.6f %.6f\n", key.c_str(), (int)r.opts.filter, r.opts.stride,
+                 r.opts.qgram, r.opts.bitmap_log2, r.opts.probe_bits, r.opts.tile_kib, r.ms, r.auto_ms);
+    std::fclose(f);
+}
+
+// Device buffers and events of one tuning run; released by the destructor.
+struct TuneRun {
+    glop_dict *h = nullptr;
+    const uint8_t *const *patterns = nullptr;
+    uint32_t n = 0;
+    const uint8_t *text = nullptr;
+    uint64_t len = 0;
+    hipStream_t s = nullptr;
+    void *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    glop_match_t *out = nullptr;
+    uint64_t cap = 0;
+    uint64_t *counts = nullptr;
+    uint64_t *total = nullptr;
+    uint32_t *bitmap = nullptr;  // largest filter bitmap (2^19 bits)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    uint64_t expect = ~0ull;     // match count every option set must give
+    uint32_t evaluated = 0;
+
+    ~TuneRun() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (void *p : {ws, (void *)out, (void *)counts, (void *)total, (void *)bitmap})
+            if (p) (void)hipFree(p);
+        if (h) glop_free(h);
+    }
+
+    int setup() {
+        ws_bytes = glop::workspace_bytes(len, h->num_cus);
+        cap = std::min<uint64_t>(len / 64 + 1024, 1ull << 20);
+        hipError_t e;
+        if ((e = hipMalloc(&ws, ws_bytes)) != hipSuccess || (e = hipMalloc((void **)&out, cap * 16)) != hipSuccess ||
+            (e = hipMalloc((void **)&counts, (uint64_t)std::max<uint32_t>(n, 1) * 8)) != hipSuccess ||
+            (e = hipMalloc((void **)&total, 8)) != hipSuccess ||
+            (e = hipMalloc((void **)&bitmap, (1u << 19) / 8)) != hipSuccess)
+            return fail(GLOP_ENOMEM, std::string("hipMalloc while tuning: ") + hipGetErrorString(e));
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+        return GLOP_OK;
+    }
+
+    // Time option set o (its free fields are resolved into o); ms = median.
+    int time(glop_build_opts &o, float *ms) {
+        glop::Compiled f;
+        f.min_len = h->c.min_len;
+        f.num_patterns = n;
+        std::string err;
+        int rc = glop::build_filter(patterns, n, o, f, err);
+        if (rc != GLOP_OK) return fail(rc, err);
+        o.filter = f.filter;
+        if (f.filter == GLOP_FILTER_QGRAM) {
+            o.stride = f.stride;
+            o.qgram = f.qgram;
+            o.bitmap_log2 = f.bitmap_log2;
+            o.probe_bits = f.probe_bits;
+        } else {
+            o.stride = o.qgram = o.bitmap_log2 = o.probe_bits = 0;
+        }
+        o.tile_kib = f.tile_kib;
+        hipError_t e = hipMemcpyAsync(bitmap, f.bitmap.data(), f.bitmap.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "bitmap upload while tuning");
+        glop::MatchLaunch a{};
+        a.d = h->dd;
+        a.d.bitmap = bitmap;
+        a.d.filter = f.filter;
+        a.d.qgram = f.qgram;
+        a.d.qmask = f.qmask;
+        a.d.stride = f.stride;
+        a.d.bitmap_log2 = f.bitmap_log2;
+        a.d.probe_bits = f.probe_bits;
+        a.d.tile_kib = f.tile_kib;
+        a.text = text;
+        a.len = len;
+        a.out = out;
+        a.max_matches = cap;
+        a.counts = counts;
+        a.total = total;
+        a.workspace = ws;
+        a.workspace_bytes = ws_bytes;
+        a.num_cus = h->num_cus;
+        constexpr int kWarm = 2, kTimed = 7;
+        float t[kTimed];
+        for (int k = 0; k < kWarm + kTimed; ++k) {
+            if (k >= kWarm && (e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((e = glop::launch_match(a, s)) != hipSuccess) return hip_fail(e, "kernel launch while tuning");
+            if (k >= kWarm) {
+                if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                    (e = hipEventElapsedTime(&t[k - kWarm], e0, e1)) != hipSuccess)
+                    return hip_fail(e, "timing while tuning");
+            }
+        }
+        uint64_t got = 0;
+        if ((e = hipMemcpy(&got, total, 8, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(e, "reading the match count while tuning");
+        if (expect == ~0ull) expect = got;
+        if (got != expect)
+            return fail(GLOP_EINTERNAL, "option sets disagree on the sample: " + std::to_string(got) + " vs " +
+                                            std::to_string(expect) + " matches");
+        std::sort(t, t + kTimed);
+        *ms = t[kTimed / 2];
+        ++evaluated;
+        return GLOP_OK;
+    }
+};
+
 }  // namespace
 
 extern "C" {
+
+int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n, const uint8_t *d_sample,
+                  uint64_t sample_len, void *stream, glop_tune_result_t *out) {
+    if (!out) return fail(GLOP_EINVAL, "NULL result");
+    if (!d_sample || sample_len == 0) return fail(GLOP_EINVAL, "the sample must be at least one byte of device text");
+    *out = glop_tune_result_t{};
+    TuneRun run;
+    run.h = make(patterns, lengths, n, nullptr, true);
+    if (!run.h) return glop_last_error();
+    run.patterns = patterns;
+    run.n = n;
+    run.text = d_sample;
+    run.len = sample_len;
+    run.s = static_cast<hipStream_t>(stream);
+    const glop::Compiled &c = run.h->c;
+    glop_build_opts cur{};
+    cur.filter = c.filter;
+    if (c.filter == GLOP_FILTER_QGRAM) {
+        cur.stride = c.stride;
+        cur.qgram = c.qgram;
+        cur.bitmap_log2 = c.bitmap_log2;
+        cur.probe_bits = c.probe_bits;
+    }
+    cur.tile_kib = c.tile_kib;
+    if (n == 0) {
+        out->opts = cur;
+        return ok();
+    }
+    const std::string key = tune_key(run.h, sample_len);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_file_read_locked();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            out->evaluated = 0;
+            out->from_cache = 1;
+            return ok();
+        }
+    }
+    int rc = run.setup();
+    if (rc != GLOP_OK) return rc;
+    float best = 0.f;
+    if ((rc = run.time(cur, &best)) != GLOP_OK) return rc;
+    const float auto_ms = best;
+    // Keep a candidate that is at least 1 % faster; options it cannot take
+    // (GLOP_EINVAL from the filter stage) are skipped.
+    auto consider = [&](glop_build_opts cand) -> int {
+        float ms = 0.f;
+        int r = run.time(cand, &ms);
+        if (r == GLOP_EINVAL) return GLOP_OK;
+        if (r != GLOP_OK) return r;
+        if (ms < 0.99f * best) {
+            best = ms;
+            cur = cand;
+        }
+        return GLOP_OK;
+    };
+    const uint32_t minlen = c.min_len;
+    glop_build_opts none{};
+    none.filter = GLOP_FILTER_NONE;
+    none.tile_kib = 8;
+    if ((rc = consider(none)) != GLOP_OK) return rc;
+    if (cur.filter == GLOP_FILTER_QGRAM) {
+        const glop_build_opts base = cur;
+        for (uint32_t q = 1; q <= std::min<uint32_t>(4, minlen); ++q) {
+            if (q == base.qgram) continue;
+            glop_build_opts cand = base;
+            cand.qgram = q;
+            cand.stride = minlen >= q + 3 ? 4u : 1u;
+            cand.bitmap_log2 = 0;
+            cand.tile_kib = 8;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
+        {
+            glop_build_opts cand = cur;
+            cand.stride = cur.stride == 4 ? 1u : 4u;
+            cand.tile_kib = 8;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
+        {
+            glop_build_opts cand = cur;
+            cand.probe_bits = cur.probe_bits == 2 ? 1u : 2u;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
+        const uint32_t lg0 = cur.bitmap_log2;
+        for (uint32_t lg = lg0 > 15 ? lg0 - 3 : 12; lg <= std::min<uint32_t>(19, lg0 + 1); ++lg) {
+            if (lg == lg0) continue;
+            glop_build_opts cand = cur;
+            cand.bitmap_log2 = lg;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
+        if (cur.stride == 4) {
+            glop_build_opts cand = cur;
+            cand.tile_kib = cur.tile_kib == 16 ? 8u : 16u;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
+    }
+    out->opts = cur;
+    out->ms = best;
+    out->auto_ms = auto_ms;
+    out->evaluated = run.evaluated;
+    out->from_cache = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = *out;
+        tune_file_append_locked(key, *out);
+    }
+    return ok();
+}
 
 glop_handle_t glop_build(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n) {
     return make(patterns, lengths, n, nullptr, true);
@@ -348,6 +631,7 @@ const char *glop_strerror(int code) {
         case GLOP_EHIP: return "HIP runtime error";
         case GLOP_ETOOLONG: return "pattern too long";
         case GLOP_ENODEV: return "no usable device";
+        case GLOP_EINTERNAL: return "internal consistency check failed";
         default: return "unknown error";
     }
 }

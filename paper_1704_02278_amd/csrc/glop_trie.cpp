@@ -30,6 +30,93 @@ uint32_t load_qgram(const uint8_t *p, uint32_t q) {
 
 }  // namespace
 
+// Filter stage: q-gram bitmap parameters and keys (Sections 2 and 5 filter
+// candidates by a short prefix before the full comparison).  Reads
+// c.min_len; sets the filter fields of c.  Patterns are not validated here.
+int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_opts &o, Compiled &c,
+                 std::string &err) {
+    if (o.filter != GLOP_FILTER_AUTO && o.filter != GLOP_FILTER_NONE && o.filter != GLOP_FILTER_QGRAM) {
+        err = "filter must be GLOP_FILTER_AUTO, GLOP_FILTER_NONE or GLOP_FILTER_QGRAM";
+        return GLOP_EINVAL;
+    }
+    try {
+        int32_t filter = o.filter == GLOP_FILTER_AUTO ? (n ? GLOP_FILTER_QGRAM : GLOP_FILTER_NONE) : o.filter;
+        if (n == 0) filter = GLOP_FILTER_NONE;
+        c.filter = filter;
+        if (filter == GLOP_FILTER_QGRAM) {
+            uint32_t q = o.qgram ? o.qgram : std::min<uint32_t>(4, c.min_len);
+            if (q < 1 || q > 4 || q > c.min_len) {
+                err = "qgram must be 1..4 and at most the shortest pattern length";
+                return GLOP_EINVAL;
+            }
+            uint32_t stride = o.stride ? o.stride : (c.min_len >= q + 3 ? 4u : 1u);
+            if (stride != 1 && stride != 4) {
+                err = "stride must be 1 or 4";
+                return GLOP_EINVAL;
+            }
+            if (stride == 4 && c.min_len < q + 3) {
+                err = "stride 4 needs every pattern to be at least qgram + 3 bytes";
+                return GLOP_EINVAL;
+            }
+            std::vector<uint32_t> keys;
+            keys.reserve((size_t)n * stride);
+            for (uint32_t j = 0; j < n; ++j)
+                for (uint32_t t = 0; t < stride; ++t) keys.push_back(load_qgram(patterns[j] + t, q));
+            std::sort(keys.begin(), keys.end());
+            keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+            uint32_t lg = o.bitmap_log2;
+            if (lg == 0) lg = std::min<uint32_t>(19, std::max<uint32_t>(12, ceil_log2(keys.size()) + 8));
+            if (lg < 12 || lg > 19) {
+                err = "bitmap_log2 must be 12..19";
+                return GLOP_EINVAL;
+            }
+            uint32_t k = o.probe_bits ? o.probe_bits : 2u;
+            if (k != 1 && k != 2) {
+                err = "probe_bits must be 1 or 2";
+                return GLOP_EINVAL;
+            }
+            c.qgram = q;
+            c.qmask = q == 4 ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
+            c.stride = stride;
+            c.bitmap_log2 = lg;
+            c.probe_bits = k;
+            c.filter_keys = keys.size();
+            c.bitmap.assign((1u << lg) / 32, 0);
+            for (uint32_t g : keys) {
+                const uint32_t s1 = glop_slot1(g, lg);
+                c.bitmap[s1 >> 5] |= 1u << (s1 & 31);
+                if (k == 2) {
+                    const uint32_t s2 = glop_slot2(g, lg);
+                    c.bitmap[s2 >> 5] |= 1u << (s2 & 31);
+                }
+            }
+        } else {
+            if (o.stride > 1 || o.qgram || o.bitmap_log2 || o.probe_bits) {
+                err = "stride/qgram/bitmap/probe options need the q-gram filter";
+                return GLOP_EINVAL;
+            }
+            c.qgram = 0;
+            c.qmask = 0;
+            c.stride = 1;
+            c.bitmap_log2 = 12;
+            c.bitmap.assign((1u << 12) / 32, 0);
+        }
+        c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
+        if (c.tile_kib != 8 && c.tile_kib != 16) {
+            err = "tile_kib must be 8 or 16";
+            return GLOP_EINVAL;
+        }
+        if (c.tile_kib == 16 && !(c.filter == GLOP_FILTER_QGRAM && c.stride == 4)) {
+            err = "16 KiB tiles need the stride-4 filter";
+            return GLOP_EINVAL;
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed while building the filter";
+        return GLOP_ENOMEM;
+    }
+    return GLOP_OK;
+}
+
 int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             const glop_build_opts *opts, Compiled &c, std::string &err) {
     glop_build_opts o{};
@@ -164,77 +251,8 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             }
         }
 
-        // Filter (q-gram bitmap) parameters and keys.
-        int32_t filter = o.filter == GLOP_FILTER_AUTO ? (n ? GLOP_FILTER_QGRAM : GLOP_FILTER_NONE) : o.filter;
-        if (n == 0) filter = GLOP_FILTER_NONE;
-        c.filter = filter;
-        if (filter == GLOP_FILTER_QGRAM) {
-            uint32_t q = o.qgram ? o.qgram : std::min<uint32_t>(4, c.min_len);
-            if (q < 1 || q > 4 || q > c.min_len) {
-                err = "qgram must be 1..4 and at most the shortest pattern length";
-                return GLOP_EINVAL;
-            }
-            uint32_t stride = o.stride ? o.stride : (c.min_len >= q + 3 ? 4u : 1u);
-            if (stride != 1 && stride != 4) {
-                err = "stride must be 1 or 4";
-                return GLOP_EINVAL;
-            }
-            if (stride == 4 && c.min_len < q + 3) {
-                err = "stride 4 needs every pattern to be at least qgram + 3 bytes";
-                return GLOP_EINVAL;
-            }
-            std::vector<uint32_t> keys;
-            keys.reserve((size_t)n * stride);
-            for (uint32_t j = 0; j < n; ++j)
-                for (uint32_t t = 0; t < stride; ++t) keys.push_back(load_qgram(patterns[j] + t, q));
-            std::sort(keys.begin(), keys.end());
-            keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-            uint32_t lg = o.bitmap_log2;
-            if (lg == 0) lg = std::min<uint32_t>(19, std::max<uint32_t>(12, ceil_log2(keys.size()) + 8));
-            if (lg < 12 || lg > 19) {
-                err = "bitmap_log2 must be 12..19";
-                return GLOP_EINVAL;
-            }
-            uint32_t k = o.probe_bits ? o.probe_bits : 2u;
-            if (k != 1 && k != 2) {
-                err = "probe_bits must be 1 or 2";
-                return GLOP_EINVAL;
-            }
-            c.qgram = q;
-            c.qmask = q == 4 ? 0xFFFFFFFFu : ((1u << (8 * q)) - 1u);
-            c.stride = stride;
-            c.bitmap_log2 = lg;
-            c.probe_bits = k;
-            c.filter_keys = keys.size();
-            c.bitmap.assign((1u << lg) / 32, 0);
-            for (uint32_t g : keys) {
-                const uint32_t s1 = glop_slot1(g, lg);
-                c.bitmap[s1 >> 5] |= 1u << (s1 & 31);
-                if (k == 2) {
-                    const uint32_t s2 = glop_slot2(g, lg);
-                    c.bitmap[s2 >> 5] |= 1u << (s2 & 31);
-                }
-            }
-        } else {
-            if (o.stride > 1 || o.qgram || o.bitmap_log2 || o.probe_bits) {
-                err = "stride/qgram/bitmap/probe options need the q-gram filter";
-                return GLOP_EINVAL;
-            }
-            c.qgram = 0;
-            c.qmask = 0;
-            c.stride = 1;
-            c.bitmap_log2 = 12;
-            c.bitmap.assign((1u << 12) / 32, 0);
-        }
-        c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
-        if (c.tile_kib != 8 && c.tile_kib != 16) {
-            err = "tile_kib must be 8 or 16";
-            return GLOP_EINVAL;
-        }
-        if (c.tile_kib == 16 && !(c.filter == GLOP_FILTER_QGRAM && c.stride == 4)) {
-            err = "16 KiB tiles need the stride-4 filter";
-            return GLOP_EINVAL;
-        }
+        const int rc = build_filter(patterns, n, o, c, err);
+        if (rc != GLOP_OK) return rc;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while compiling the dictionary";
         return GLOP_ENOMEM;

@@ -28,6 +28,12 @@ struct Compiled {
 int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             const glop_build_opts *opts, Compiled &out, std::string &err);
 
+// The filter stage of compile() alone: from c.min_len and the options, set
+// c's filter fields (filter, qgram, qmask, stride, bitmap_log2, probe_bits,
+// tile_kib, filter_keys, bitmap).  The trie fields of c are left as they are.
+int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_opts &o, Compiled &c,
+                 std::string &err);
+
 // CPU failureless-trie walk over a compiled dictionary (timing baseline).
 int cpu_walk(const Compiled &c, const uint8_t *text, uint64_t len, glop_match_t *out,
              uint64_t max_matches, uint64_t *counts, uint64_t *total, int threads);

@@ -129,3 +129,14 @@ def test_size_getters_and_stream_probe_argument_checks():
     assert glop.glop_stream_read(None, 0, None, None) == glop.GLOP_EINVAL
     assert glop.glop_stream_read(17, 64, 4096, None) == glop.GLOP_EINVAL
     assert glop.glop_stream_read(None, 16, 4096, None) == glop.GLOP_EINVAL
+
+
+def test_autotune_argument_checks_need_no_device():
+    pats = [b"abc", b"abd"]
+    keep, ptrs, lens, n = glop._pattern_arrays(pats)
+    r = glop.glop_tune_result_t()
+    u8pp = glop._u8pp
+    assert glop.glop_autotune(ctypes.cast(ptrs, u8pp), lens, n, 4096, 64, None, None) == glop.GLOP_EINVAL
+    assert glop.glop_autotune(ctypes.cast(ptrs, u8pp), lens, n, None, 64, None, ctypes.byref(r)) == glop.GLOP_EINVAL
+    assert glop.glop_autotune(ctypes.cast(ptrs, u8pp), lens, n, 4096, 0, None, ctypes.byref(r)) == glop.GLOP_EINVAL
+    assert glop.glop_strerror(glop.GLOP_EINTERNAL) == b"internal consistency check failed"
