@@ -267,6 +267,62 @@ def bench_batched(reps: int) -> dict:
     }
 
 
+def bench_served(requests: int, rates=(1000.0, 5000.0, 20000.0)) -> dict:
+    """Open-loop traces over 8 resident dictionaries: continuous batching vs one
+    plain call per request (FIFO, one stream).  Latency = result visible on the
+    host minus scheduled arrival; payloads are already in HBM."""
+    import torch
+
+    import paper_1704_02278_amd as glop
+    import synth
+
+    pool = 256 << 20
+    t0 = time.perf_counter()
+    dicts, pools = synth.make_served(pool_bytes=pool)
+    log(f"[bench] served: {len(dicts)} dictionaries ({', '.join(str(len(d)) for d in dicts)} patterns), "
+        f"{len(pools)} x {pool >> 20} MiB pools, generated in {time.perf_counter() - t0:.1f} s")
+    dev_pools = [torch.from_numpy(p).cuda() for p in pools]
+    del pools
+    t0 = time.perf_counter()
+    handles = [glop.Dict(d) for d in dicts]
+    log(f"[bench] served: dictionaries built in {time.perf_counter() - t0:.1f} s")
+
+    def pct(a, q):
+        return round(float(np.percentile(a, q)) / 1e6, 4)
+
+    def run(mode, trace, budget=0):
+        at, dk, sz, off = trace
+        texts = np.array([dev_pools[dk[k]].data_ptr() + int(off[k]) for k in range(len(sz))], dtype=np.uint64)
+        srv = glop.Server(handles, mode=mode, hbm_budget_bytes=budget)
+        try:
+            lat, matches, trunc, batch, wall = srv.run_trace(dk, texts, sz, at)
+        finally:
+            srv.close()
+        assert not trunc.any()
+        res = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": round(float(lat.mean()) / 1e6, 4),
+               "GBps": round(float(sz.sum()) / (wall / 1e9) / 1e9, 2), "wall_s": round(wall / 1e9, 3)}
+        if mode == glop.GLOP_SERVE_BATCHED:
+            res["mean_batch_requests"] = round(float(batch.mean()), 2)
+        return res, matches
+
+    out = {"workload": f"{len(dicts)} resident dictionaries ({'/'.join(str(len(d)) for d in dicts)} patterns); "
+                       f"Poisson arrivals; sizes lognormal (median 256 KiB, sigma 2.16) in [4 KiB, 16 MiB]",
+           "requests_per_rate": requests, "rates": {}}
+    for k, rate in enumerate(rates):
+        trace = synth.served_trace(rate, requests, len(dicts), pool, trace_id=k)
+        log(f"[bench] served: {rate:.0f} req/s, {requests} requests, {int(trace[2].sum()) / 2**30:.1f} GiB ...")
+        b, mb = run(glop.GLOP_SERVE_BATCHED, trace)
+        p, mp = run(glop.GLOP_SERVE_PLAIN, trace)
+        assert np.array_equal(mb, mp), "batched and plain disagree on a request's match count"
+        out["rates"][f"{rate:.0f}"] = {"offered_GBps": round(float(trace[2].sum()) / (trace[0][-1] / 1e9) / 1e9, 2),
+                                       "batched": b, "plain": p, "matches": int(mb.sum())}
+    trace = synth.served_trace(rates[-1], requests, len(dicts), pool, trace_id=len(rates))
+    log("[bench] served: 256 MiB budget ...")
+    b, _ = run(glop.GLOP_SERVE_BATCHED, trace, budget=256 << 20)
+    out["budget_256MiB"] = {"rate": rates[-1], "batched": b}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +334,8 @@ def main() -> int:
     ap.add_argument("--copy-probe", action="store_true", help="also time a plain device copy of the text")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (many texts) comparison")
     ap.add_argument("--batched-reps", type=int, default=10)
+    ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) traces")
+    ap.add_argument("--served-requests", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the matcher has no multi-GPU path "
@@ -424,6 +482,9 @@ def main() -> int:
         torch.cuda.empty_cache()
         log("[bench] batched comparison ...")
         result["batched"] = bench_batched(args.batched_reps)
+    if not args.no_served and args.workload == "medium":
+        torch.cuda.empty_cache()
+        result["served"] = bench_served(args.served_requests)
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(text, pats, args.cpu_seconds)

@@ -282,6 +282,115 @@ int glop_get_info(glop_handle_t h, glop_info_t *out);
 uint32_t glop_num_patterns(glop_handle_t h);
 uint32_t glop_max_len(glop_handle_t h);
 
+/* ---- Served matching: resident dictionaries, continuous batching ---------------
+ *
+ * A server holds several dictionaries resident on one device and matches
+ * requests (device-resident texts, each tagged with one dictionary) as they
+ * arrive.  A scheduler thread forms batches continuously: whenever one of its
+ * stream slots is free it takes the dictionary whose oldest waiting request
+ * arrived first and packs that dictionary's waiting requests, oldest first,
+ * into one glop_match_batch launch, up to max_batch_requests requests and
+ * max_batch_bytes bytes, and as far as the HBM budget allows.  Requests that
+ * arrive while batches run join the next launch.  The paper streams batches
+ * of logs through the device so transfers overlap matching (Section 6) and
+ * names real-time operation as future work (Section 8); this is that
+ * operation for many concurrent streams.
+ *
+ * HBM budget: a request holds its payload bytes (if count_payload), its
+ * output capacity (16 bytes per record, max(64, len / 256) records) and its
+ * share of the batch workspace from admission until it is released.  A
+ * request that does not fit waits; one that could never fit fails at submit.
+ *
+ * Plain mode (mode = GLOP_SERVE_PLAIN) is the baseline: no batching, every
+ * request is one glop_match_ws call, in arrival order, on one stream.
+ *
+ * Results: a completion names the request, its record count and a device
+ * pointer to its records (offsets relative to its own text, ascending, then
+ * pattern ids ascending, as glop_match).  Records beyond the request's output
+ * capacity are not written (truncated = 1; the count stays exact).  They stay
+ * valid until glop_server_release(request id).  Results do not depend on
+ * which requests share a batch.
+ *
+ * Threads: submit, poll and release may be called from any threads.  The
+ * texts must stay valid and unchanged until the request completes.  Handles
+ * added to a server must outlive it.
+ */
+#define GLOP_SERVE_BATCHED 0
+#define GLOP_SERVE_PLAIN 1
+
+typedef struct glop_server *glop_server_t;
+
+typedef struct {
+    int32_t mode;                /* GLOP_SERVE_BATCHED or GLOP_SERVE_PLAIN */
+    uint32_t max_inflight;       /* batches in flight at once (stream slots); 0 = 2 */
+    uint32_t max_batch_requests; /* 0 = 4096 */
+    uint64_t max_batch_bytes;    /* 0 = 1 GiB */
+    uint64_t hbm_budget_bytes;   /* 0 = 4 GiB */
+    uint32_t count_payload;      /* 1: payload bytes count against the budget */
+    uint32_t reserved;
+} glop_server_opts;
+
+typedef struct {
+    uint64_t request_id;
+    uint64_t tag;                  /* the caller's tag from submit */
+    uint32_t dict;                 /* dictionary index */
+    uint32_t truncated;            /* 1 if records were cut at the output capacity */
+    uint64_t matches;              /* number of (offset, id) records of the request */
+    uint64_t records;              /* records written at d_records (matches unless truncated) */
+    const glop_match_t *d_records; /* device records of the request */
+    int64_t arrival_ns;            /* arrival time given at submit (steady clock) */
+    int64_t launch_ns;             /* when its batch was launched */
+    int64_t done_ns;               /* when the scheduler saw its batch finish */
+    uint32_t batch_requests;       /* requests in its batch */
+    uint32_t reserved;
+} glop_completion_t;
+
+/* Create a server on the current device (opts may be NULL = defaults).
+ * NULL on error (glop_last_error: GLOP_EINVAL for a bad mode, GLOP_EHIP,
+ * GLOP_ENOMEM). */
+glop_server_t glop_server_create(const glop_server_opts *opts);
+
+/* Make dictionary h resident as index *dict (0, 1, ... in call order). */
+int glop_server_add_dict(glop_server_t s, glop_handle_t h, uint32_t *dict);
+
+/* Enqueue a request; arrival_ns is its arrival time on the steady clock
+ * (glop_now_ns), or a negative value for "now".  *request_id receives its id.
+ * Errors: GLOP_EINVAL (bad dictionary, NULL text with len > 0, a request
+ * larger than the whole budget or than max_batch_bytes). */
+int glop_server_submit(glop_server_t s, uint32_t dict, const uint8_t *d_text, uint64_t len, uint64_t tag,
+                       int64_t arrival_ns, uint64_t *request_id);
+
+/* Take up to max completions, waiting up to wait_us microseconds for the
+ * first one; *n receives how many were written. */
+int glop_server_poll(glop_server_t s, glop_completion_t *out, uint32_t max, uint32_t wait_us, uint32_t *n);
+
+/* Release a completed request's records and HBM budget. */
+int glop_server_release(glop_server_t s, uint64_t request_id);
+
+/* Stop accepting releases, finish all submitted work, stop the scheduler and
+ * free everything.  Records of completed requests, released or not, are
+ * invalid once this is called. */
+void glop_server_destroy(glop_server_t s);
+
+/* Steady-clock time in nanoseconds (the clock of arrival_ns). */
+int64_t glop_now_ns(void);
+
+/* Open-loop trace replay (measurement): submit request k at t0 + at_ns[k]
+ * from a submitter thread (t0 = the call's start), poll completions, record
+ * each request's latency from its scheduled arrival to the moment its result
+ * was visible on the host, and release it.  If copy_out is non-NULL, each
+ * request's records are first copied (device to device) to
+ * copy_out + copy_base[k] (records), at most copy_cap[k] of them.
+ *   dicts, texts, lens, at_ns: n requests (at_ns ascending).
+ *   latency_ns, matches, truncated: n outputs; batch_requests: n outputs or
+ *   NULL (requests in the batch that served each one).
+ *   *wall_ns: first scheduled arrival to last completion seen.
+ */
+int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, const uint8_t *const *texts,
+                          const uint64_t *lens, const int64_t *at_ns, glop_match_t *copy_out,
+                          const uint64_t *copy_base, const uint64_t *copy_cap, int64_t *latency_ns,
+                          uint64_t *matches, uint32_t *truncated, uint32_t *batch_requests, int64_t *wall_ns);
+
 /* ---- Autotuning ---------------------------------------------------------------
  *
  * glop_autotune: choose build options for a dictionary by timing them on a

@@ -32,6 +32,8 @@ GLOP_EHIP = -3
 GLOP_ETOOLONG = -4
 GLOP_ENODEV = -5
 GLOP_EINTERNAL = -6
+GLOP_SERVE_BATCHED = 0
+GLOP_SERVE_PLAIN = 1
 GLOP_FILTER_AUTO = 0
 GLOP_FILTER_NONE = 1
 GLOP_FILTER_QGRAM = 2
@@ -63,6 +65,19 @@ class glop_events_t(ctypes.Structure):
 class glop_tune_result_t(ctypes.Structure):
     _fields_ = [("opts", glop_build_opts), ("ms", ctypes.c_float), ("auto_ms", ctypes.c_float),
                 ("evaluated", ctypes.c_uint32), ("from_cache", ctypes.c_uint32)]
+
+
+class glop_server_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_inflight", ctypes.c_uint32), ("max_batch_requests", ctypes.c_uint32),
+                ("max_batch_bytes", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("count_payload", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class glop_completion_t(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("dict", ctypes.c_uint32),
+                ("truncated", ctypes.c_uint32), ("matches", ctypes.c_uint64), ("records", ctypes.c_uint64),
+                ("d_records", ctypes.c_void_p), ("arrival_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch_requests", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class glop_info_t(ctypes.Structure):
@@ -101,6 +116,17 @@ _SIGNATURES = {
     "glop_stream_read": (ctypes.c_int, [_vp, _u64, _vp, _vp]),
     "glop_autotune": (ctypes.c_int, [_u8pp, _u32p, ctypes.c_uint32, _vp, _u64, _vp,
                                      ctypes.POINTER(glop_tune_result_t)]),
+    "glop_server_create": (_vp, [ctypes.POINTER(glop_server_opts)]),
+    "glop_server_add_dict": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "glop_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _u64, _u64, ctypes.c_int64,
+                                          ctypes.POINTER(_u64)]),
+    "glop_server_poll": (ctypes.c_int, [_vp, ctypes.POINTER(glop_completion_t), ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint32)]),
+    "glop_server_release": (ctypes.c_int, [_vp, _u64]),
+    "glop_server_destroy": (None, [_vp]),
+    "glop_now_ns": (ctypes.c_int64, []),
+    "glop_server_run_trace": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp, ctypes.POINTER(ctypes.c_int64)]),
     "glop_last_error": (ctypes.c_int, []),
     "glop_last_error_message": (ctypes.c_char_p, []),
     "glop_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -340,4 +366,80 @@ def autotune(patterns, sample, stream=None) -> dict:
                      "probe_bits": o.probe_bits, "tile_kib": o.tile_kib},
             "ms": float(r.ms), "auto_ms": float(r.auto_ms), "evaluated": int(r.evaluated),
             "from_cache": bool(r.from_cache)}
+
+
+class Server:
+    """Resident dictionaries matched as requests arrive (continuous batching).
+
+    ``Server(dicts, mode=GLOP_SERVE_BATCHED, hbm_budget_bytes=..., ...)`` with
+    ``dicts`` a list of ``Dict``; ``submit`` / ``poll`` / ``release`` map to the
+    C calls, and ``run_trace`` replays an open-loop trace natively.
+    """
+
+    def __init__(self, dicts, *, mode=GLOP_SERVE_BATCHED, max_inflight=0, max_batch_requests=0, max_batch_bytes=0,
+                 hbm_budget_bytes=0, count_payload=True):
+        o = glop_server_opts(mode, max_inflight, max_batch_requests, max_batch_bytes, hbm_budget_bytes,
+                             1 if count_payload else 0, 0)
+        h = glop_server_create(ctypes.byref(o))
+        if not h:
+            raise GlopError(glop_last_error(), "glop_server_create")
+        self._s = ctypes.c_void_p(h)
+        self.dicts = list(dicts)
+        for d in self.dicts:
+            k = ctypes.c_uint32()
+            _check(glop_server_add_dict(self._s, d.handle, ctypes.byref(k)), "glop_server_add_dict")
+
+    def submit(self, dict_index, text, tag=0, length=None, arrival_ns=-1) -> int:
+        rid = ctypes.c_uint64()
+        n = int(text.numel()) if length is None else int(length)
+        _check(glop_server_submit(self._s, dict_index, text.data_ptr() if n else None, n, tag, arrival_ns,
+                                  ctypes.byref(rid)), "glop_server_submit")
+        return rid.value
+
+    def poll(self, max_n=256, wait_us=1000):
+        buf = (glop_completion_t * max_n)()
+        got = ctypes.c_uint32()
+        _check(glop_server_poll(self._s, buf, max_n, wait_us, ctypes.byref(got)), "glop_server_poll")
+        return [buf[k] for k in range(got.value)]
+
+    def release(self, request_id):
+        _check(glop_server_release(self._s, request_id), "glop_server_release")
+
+    def run_trace(self, dicts, texts, lengths, at_ns, copy_out=None, copy_base=None, copy_cap=None):
+        """Replay n requests (device pointers ``texts``); returns (latency_ns, matches,
+        truncated, batch_requests, wall_ns) as numpy arrays / int."""
+        import numpy as np
+
+        n = len(lengths)
+        dk = np.ascontiguousarray(dicts, dtype=np.uint32)
+        tx = np.ascontiguousarray(texts, dtype=np.uint64)
+        ln = np.ascontiguousarray(lengths, dtype=np.uint64)
+        at = np.ascontiguousarray(at_ns, dtype=np.int64)
+        lat = np.zeros(n, dtype=np.int64)
+        mt = np.zeros(n, dtype=np.uint64)
+        tr = np.zeros(n, dtype=np.uint32)
+        br = np.zeros(n, dtype=np.uint32)
+        wall = ctypes.c_int64()
+        cb = cc = None
+        if copy_out is not None:
+            cb = np.ascontiguousarray(copy_base, dtype=np.uint64)
+            cc = np.ascontiguousarray(copy_cap, dtype=np.uint64)
+        _check(glop_server_run_trace(self._s, n, dk.ctypes.data, tx.ctypes.data, ln.ctypes.data, at.ctypes.data,
+                                     copy_out.data_ptr() if copy_out is not None else None,
+                                     cb.ctypes.data if cb is not None else None,
+                                     cc.ctypes.data if cc is not None else None,
+                                     lat.ctypes.data, mt.ctypes.data, tr.ctypes.data, br.ctypes.data,
+                                     ctypes.byref(wall)), "glop_server_run_trace")
+        return lat, mt, tr, br, int(wall.value)
+
+    def close(self):
+        if getattr(self, "_s", None):
+            glop_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 

@@ -21,7 +21,7 @@ import isa_check  # noqa: E402  (a sibling module; the package itself is not imp
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libglop.so"
-SOURCES = ["glop_capi.cpp", "glop_trie.cpp", "glop_kernels.hip"] + [
+SOURCES = ["glop_capi.cpp", "glop_trie.cpp", "glop_serve.cpp", "glop_kernels.hip"] + [
     f"glop_kernels_{tag}.hip" for tag in "abcdef"
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -170,6 +170,14 @@ int check_match_args(const glop_dict *h, const uint8_t *text, uint64_t len, cons
     return GLOP_OK;
 }
 
+}  // namespace
+
+namespace glop {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+}  // namespace glop
+
+namespace {
+
 // ---- Autotuning --------------------------------------------------------------
 
 uint32_t ceil_log2_u64(uint64_t v) {

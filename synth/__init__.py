@@ -17,6 +17,12 @@ generators stand in for them with the shapes of the workloads studied here:
 * ``batched`` (``make_chunks``) -- the medium dictionary over 4,096 independent
   texts whose sizes are lognormal (median 256 KiB, sigma 2.16) clipped to
   [1 KiB, 64 MiB], about 8 GiB in all, 1 plant / 64 KiB in each
+* served (``make_served``, ``served_trace``) -- 8 resident dictionaries of
+  100 ... 20,000 patterns (the medium recipe up to 1,000 patterns, the large
+  one above), a 256 MiB planted text pool per dictionary, and request traces
+  with Poisson arrivals, a uniform dictionary tag and lognormal sizes (median
+  256 KiB, sigma 2.16) clipped to [4 KiB, 16 MiB], each request a slice of its
+  dictionary's pool
 
 Every random draw comes from MT19937-64 substreams (``synth.c``) selected by
 (seed, stream, block), so the output does not depend on thread counts.
@@ -46,6 +52,8 @@ STREAM_PLANTS = 3 << 20
 # Chunked workloads: sizes, then (text, plants) per chunk.
 STREAM_CHUNK_SIZES = 4 << 20
 STREAM_CHUNKS = 5 << 20
+# Served workload: dictionaries, pools and traces.
+STREAM_SERVED = 6 << 20
 
 
 def build_library(force: bool = False) -> Path:
@@ -398,4 +406,48 @@ def make_chunks(name: str = "batched", seed: int = BASE_SEED, count: int | None 
         plants.append(plant(view, pats, spec.plant_every, seed, STREAM_CHUNKS + 2 * k + 1,
                             draw_chunk=64 + 4 * (n // spec.plant_every)))
     return pats, text, offsets, sizes, plants
+
+
+SERVED_SIZES = (100, 500, 1000, 2000, 5000, 10000, 15000, 20000)
+
+
+def served_spec(n: int) -> PatternSpec:
+    """Dictionary recipe by size: medium's up to 1,000 patterns, large's above."""
+    base = WORKLOADS["medium" if n <= 1000 else "large"].patterns
+    return dataclasses.replace(base, n=n)
+
+
+def make_served(pool_bytes: int = 256 << 20, seed: int = BASE_SEED, sizes=SERVED_SIZES, threads: int | None = None):
+    """(dictionaries, pools): one pattern list and one planted text pool per size."""
+    dicts, pools = [], []
+    for k, n in enumerate(sizes):
+        pats = gen_patterns(served_spec(n), seed, STREAM_SERVED + 16 * k)
+        spec = dataclasses.replace(WORKLOADS["medium"].text, n_bytes=pool_bytes)
+        pool = gen_text(spec, seed, STREAM_SERVED + 16 * k + 1, threads=threads)
+        plant(pool, pats, spec.plant_every, seed, STREAM_SERVED + 16 * k + 2)
+        dicts.append(pats)
+        pools.append(pool)
+    return dicts, pools
+
+
+def served_trace(rate: float, count: int, ndicts: int, pool_bytes: int, seed: int = BASE_SEED,
+                 size_min: int = 4 << 10, size_max: int = 16 << 20, median: int = 256 << 10,
+                 sigma: float = 2.16, trace_id: int = 0):
+    """Open-loop request trace: (arrival ns, dictionary, size, offset in its pool), arrivals ascending."""
+    d = Draws(seed, STREAM_SERVED + 1024 + trace_id)
+    t = 0.0
+    at, dk, sz, off = [], [], [], []
+    mu = float(np.log(median))
+    for _ in range(count):
+        t += -np.log(1.0 - d.unit()) / rate
+        u1, u2 = 1.0 - d.unit(), d.unit()
+        z = float(np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
+        n = min(max(int(round(float(np.exp(mu + sigma * z)))), size_min), min(size_max, pool_bytes))
+        k = d.randint(0, ndicts - 1)
+        at.append(int(t * 1e9))
+        dk.append(k)
+        sz.append(n)
+        off.append(d.randint(0, pool_bytes - n))
+    return (np.array(at, dtype=np.int64), np.array(dk, dtype=np.uint32), np.array(sz, dtype=np.uint64),
+            np.array(off, dtype=np.uint64))
 

@@ -140,3 +140,17 @@ def test_autotune_argument_checks_need_no_device():
     assert glop.glop_autotune(ctypes.cast(ptrs, u8pp), lens, n, None, 64, None, ctypes.byref(r)) == glop.GLOP_EINVAL
     assert glop.glop_autotune(ctypes.cast(ptrs, u8pp), lens, n, 4096, 0, None, ctypes.byref(r)) == glop.GLOP_EINVAL
     assert glop.glop_strerror(glop.GLOP_EINTERNAL) == b"internal consistency check failed"
+
+
+def test_server_create_argument_checks():
+    bad = glop.glop_server_opts(7, 0, 0, 0, 0, 1, 0)
+    assert not glop.glop_server_create(ctypes.byref(bad))
+    assert glop.glop_last_error() == glop.GLOP_EINVAL
+    assert glop.glop_server_add_dict(None, None, None) == glop.GLOP_EINVAL
+    assert glop.glop_server_release(None, 1) == glop.GLOP_EINVAL
+    assert glop.glop_server_submit(None, 0, None, 0, 0, -1, None) == glop.GLOP_EINVAL
+    got = ctypes.c_uint32()
+    assert glop.glop_server_poll(None, None, 0, 0, ctypes.byref(got)) == glop.GLOP_EINVAL
+    glop.glop_server_destroy(None)  # ignored
+    t0 = glop.glop_now_ns()
+    assert glop.glop_now_ns() >= t0 > 0
