@@ -143,6 +143,36 @@ def cpu_trie_baseline(d, text: np.ndarray, target_s: float) -> dict:
     return {"kind": "failureless-trie walk on the host (the paper's CPU counterpart)", **out}
 
 
+def bench_host_stream(d, text: np.ndarray, reps: int = 3, chunk_bytes: int = 64 << 20) -> dict:
+    """The same text matched from host memory (glop_match_host): pageable and
+    pinned sources, end to end (host text in, device result out), next to the
+    plain pinned H2D copy rate of the same bytes."""
+    import torch
+
+    n = int(text.size)
+    pinned = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    pinned.numpy()[:] = text
+    dev = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        dev.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dev.copy_(pinned, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = n * reps / (time.perf_counter() - t0) / 1e9
+    del dev
+    out = {"chunk_bytes": chunk_bytes, "h2d_pinned_GBps": round(h2d, 2)}
+    for name, src in (("pageable", text), ("pinned", pinned.numpy())):
+        d.match_host(src, chunk_bytes=chunk_bytes)  # warm-up (sizes the output)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            d.match_host(src, chunk_bytes=chunk_bytes, max_matches=1 << 20)
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": round(dt * 1e3, 3), "GBps": round(n / dt / 1e9, 2), "frac_of_h2d": round(n / dt / 1e9 / h2d, 3)}
+    return out
+
+
 def bench_batched(reps: int) -> dict:
     """Many independent texts: one batched call (graph replay) vs one plain call per text.
 
@@ -335,6 +365,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (many texts) comparison")
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) traces")
+    ap.add_argument("--no-host-stream", action="store_true", help="skip the host-streamed input measurement")
     ap.add_argument("--served-requests", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -477,6 +508,29 @@ def main() -> int:
     }
     if copy:
         result["copy_probe"] = copy
+    # The truncated-trie engine (prefix 8 + GPU verify) on the same text: same
+    # records, different walk and verify cost.
+    d8 = glop.Dict(pats, prefix_len=8)
+    for _ in range(args.warmup):
+        d8.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    assert int(total.item()) == got_total, "prefix-8 engine disagrees with the full trie"
+    a8 = torch.cuda.Event(enable_timing=True)
+    b8 = torch.cuda.Event(enable_timing=True)
+    a8.record(stream)
+    for _ in range(args.steps):
+        d8.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
+    b8.record(stream)
+    torch.cuda.synchronize()
+    ms8 = a8.elapsed_time(b8) / args.steps
+    result["prefix8"] = {"ms_per_step": round(ms8, 5), "GBps": round(n / (ms8 / 1e3) / 1e9, 2),
+                         "vs_full_trie": round(ms_per_step / ms8, 3), "num_states": d8.info()["num_states"],
+                         "engine": "trie of 8-byte prefixes + GPU verify of the rest (exact)"}
+    del d8
+
+    if not args.no_host_stream:
+        log("[bench] host-streamed input ...")
+        result["host_streamed"] = bench_host_stream(d, text)
     if not args.no_batched and args.workload == "medium":
         del out, ws_buf, t_dev
         torch.cuda.empty_cache()

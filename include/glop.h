@@ -64,7 +64,8 @@ typedef struct glop_dict *glop_handle_t;
 
 /*
  * Build options (glop_build_ex).  Zero-initialise and set what you need; every
- * setting changes only how the work is done, never the result.
+ * setting except `candidates` changes only how the work is done, never the
+ * result.
  *
  *   filter      GLOP_FILTER_AUTO (0) = automatic (the q-gram filter whenever the
  *                    dictionary is not empty);
@@ -87,6 +88,15 @@ typedef struct glop_dict *glop_handle_t;
  *   tile_kib    0 = automatic (8); 8 or 16: bytes of text one wavefront streams
  *               per tile (16 bytes per lane per round, 8 or 16 rounds).  16 is
  *               available with the stride-4 filter only.
+ *   prefix_len  0 = the trie holds the whole patterns; 1..255 = the trie holds
+ *               each pattern's first prefix_len bytes only (the library of
+ *               Sections 2 and 5 truncates patterns to 8 characters), and a
+ *               verify stage on the GPU compares the rest of every candidate
+ *               against its full pattern, so the result is still exact.
+ *   candidates  with prefix_len: 1 = report the unverified candidates instead,
+ *               i.e. every (offset, id) whose first min(prefix_len, length)
+ *               bytes match (the truncated matching of Sections 2 and 5, which
+ *               can report false positives).  This changes the result.
  */
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1
@@ -98,6 +108,8 @@ typedef struct {
     uint32_t bitmap_log2;
     uint32_t probe_bits;
     uint32_t tile_kib;
+    uint32_t prefix_len;
+    uint32_t candidates;
 } glop_build_opts;
 
 /*
@@ -161,6 +173,32 @@ void glop_free(glop_handle_t h);
  */
 int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
                uint64_t max_matches, uint64_t *d_counts, void *stream);
+
+/*
+ * Match a text held in host memory (any pageable buffer).  The text is
+ * streamed to the device in pieces of chunk_bytes start offsets, each piece
+ * carrying the next max_len - 1 bytes as well (Section 4: consecutive chunks
+ * overlap by the longest pattern minus one, so no occurrence is cut).  Two
+ * pinned staging buffers and two device buffers form a pipeline: host
+ * threads copy piece k+1 into pinned memory and a copy stream moves it to the
+ * device while piece k is matched on `stream` (Section 6: streams overlap the
+ * next batch's transfer with the kernel).  Every piece adds its records to
+ * one output in order and its counts to one set of counts, so the result is
+ * exactly glop_match's on the whole text.  A text already in pinned host
+ * memory (hipHostMalloc, or a pinned torch tensor) is uploaded from where it
+ * is, without the staging copy.
+ *
+ *   h_text, len   host text (not modified; read during the call only).
+ *   d_out, max_matches, d_counts   as for glop_match.
+ *   d_total       device uint64_t for the record total, or NULL.
+ *   chunk_bytes   start offsets per piece; 0 = 64 MiB; at least 4096.
+ *   stream        hipStream_t or NULL; the call returns after the result is
+ *                 complete on the device (it synchronizes the stream).
+ * Errors: GLOP_EINVAL, GLOP_ENODEV, GLOP_ENOMEM, GLOP_EHIP.
+ */
+int glop_match_host(glop_handle_t h, const uint8_t *h_text, uint64_t len, glop_match_t *d_out,
+                    uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, uint64_t chunk_bytes,
+                    void *stream);
 
 /* Bytes of device workspace glop_match_ws needs for a text of len bytes. */
 uint64_t glop_workspace_bytes(glop_handle_t h, uint64_t len);
@@ -270,6 +308,8 @@ typedef struct {
     int32_t filter;          /* GLOP_FILTER_NONE or GLOP_FILTER_QGRAM as chosen */
     uint32_t stride, qgram, bitmap_log2, probe_bits, tile_kib;
     uint64_t filter_keys;    /* distinct q-grams set in the bitmap */
+    uint32_t prefix_len;     /* 0, or the trie's truncation length */
+    uint32_t candidates;     /* 1 if unverified prefix candidates are reported */
     uint64_t device_bytes;   /* device memory held by the handle */
     int32_t device;          /* HIP device id, or -1 for a host-only handle */
 } glop_info_t;

@@ -47,7 +47,8 @@ class glop_match_t(ctypes.Structure):
 
 class glop_build_opts(ctypes.Structure):
     _fields_ = [("filter", ctypes.c_int32), ("stride", ctypes.c_uint32), ("qgram", ctypes.c_uint32),
-                ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32)]
+                ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32),
+                ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32)]
 
 
 class glop_chunk_t(ctypes.Structure):
@@ -87,6 +88,7 @@ class glop_info_t(ctypes.Structure):
         ("outlist_ids", ctypes.c_uint64), ("filter", ctypes.c_int32), ("stride", ctypes.c_uint32),
         ("qgram", ctypes.c_uint32), ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32),
         ("tile_kib", ctypes.c_uint32), ("filter_keys", ctypes.c_uint64),
+        ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
         ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
     ]
 
@@ -106,6 +108,7 @@ _SIGNATURES = {
     "glop_workspace_bytes": (_u64, [_vp, _u64]),
     "glop_match_ws": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _vp,
                                      ctypes.POINTER(glop_events_t)]),
+    "glop_match_host": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]),
     "glop_batch_workspace_bytes": (_u64, [_vp, ctypes.c_uint32, _u64]),
     "glop_match_batch": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64,
                                         _vp]),
@@ -160,17 +163,19 @@ def _pattern_arrays(patterns):
     return keep, ptrs, lens, len(pats)
 
 
-def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0, tile_kib=0):
-    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits), int(tile_kib))
+def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0, tile_kib=0, prefix_len=0,
+          candidates=False):
+    return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits), int(tile_kib),
+                           int(prefix_len), 1 if candidates else 0)
 
 
 class Dict:
     """A compiled dictionary on the current device (or host-only with ``device=False``)."""
 
     def __init__(self, patterns, *, device: bool = True, filter=GLOP_FILTER_AUTO, stride=0, qgram=0,
-                 bitmap_log2=0, probe_bits=0, tile_kib=0):
+                 bitmap_log2=0, probe_bits=0, tile_kib=0, prefix_len=0, candidates=False):
         keep, ptrs, lens, n = _pattern_arrays(patterns)
-        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits, tile_kib)
+        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits, tile_kib, prefix_len, candidates)
         fn = glop_build_ex if device else glop_compile
         h = fn(ctypes.cast(ptrs, _u8pp), lens, n, ctypes.byref(opts))
         if not h:
@@ -242,6 +247,34 @@ class Dict:
             cap = got
             out = torch.empty((cap, 2), dtype=torch.int64, device=dev)
             self.match_into(text, out, counts, max_matches=cap, total=total, workspace=ws, stream=stream)
+            got = int(total.item())
+        k = min(cap, got)
+        return out[:k, 0], out[:k, 1], counts[: self.num_patterns], got
+
+    def match_host(self, text, max_matches=None, chunk_bytes=0, stream=None):
+        """Match a host (numpy uint8) text streamed through pinned buffers
+        (glop_match_host); returns (offsets, ids, counts, total) on the device,
+        like ``match``.  ``max_matches=None`` sizes the output (a second pass
+        streams the text again if the first guess was short)."""
+        import numpy as np
+        import torch
+
+        t = np.ascontiguousarray(text, dtype=np.uint8)
+        n = int(t.size)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        counts = torch.empty(max(1, self.num_patterns), dtype=torch.int64, device=dev)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        cap = max(1024, n // 1024) if max_matches is None else int(max_matches)
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=dev)
+        s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+        _check(glop_match_host(self._h, t.ctypes.data if n else None, n, out.data_ptr(), cap, counts.data_ptr(),
+                               total.data_ptr(), int(chunk_bytes), s), "glop_match_host")
+        got = int(total.item())
+        if max_matches is None and got > cap:
+            cap = got
+            out = torch.empty((cap, 2), dtype=torch.int64, device=dev)
+            _check(glop_match_host(self._h, t.ctypes.data if n else None, n, out.data_ptr(), cap,
+                                   counts.data_ptr(), total.data_ptr(), int(chunk_bytes), s), "glop_match_host")
             got = int(total.item())
         k = min(cap, got)
         return out[:k, 0], out[:k, 1], counts[: self.num_patterns], got

@@ -9,6 +9,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "glop.h"
 #include "glop_kernels.hpp"
@@ -77,7 +79,10 @@ int upload(glop_dict *h) {
     const uint64_t o_delta = align256(o_bm + c.bitmap.size() * 4);
     const uint64_t o_term = align256(o_delta + c.delta.size() * 4);
     const uint64_t o_out = align256(o_term + c.term.size() * 4);
-    const uint64_t bytes = align256(o_out + (c.outids.size() + 1) * 4);
+    const uint64_t o_pbytes = align256(o_out + (c.outids.size() + 1) * 4);
+    const uint64_t o_poff = align256(o_pbytes + c.pat_bytes.size());
+    const uint64_t o_plen = align256(o_poff + c.pat_off.size() * 8);
+    const uint64_t bytes = align256(o_plen + c.pat_len.size() * 4);
     void *blob = nullptr;
     e = hipMalloc(&blob, bytes);
     if (e != hipSuccess) return fail(GLOP_ENOMEM, std::string("hipMalloc of the dictionary: ") + hipGetErrorString(e));
@@ -90,7 +95,10 @@ int upload(glop_dict *h) {
                   {o_bm, c.bitmap.data(), c.bitmap.size() * 4},
                   {o_delta, c.delta.data(), c.delta.size() * 4},
                   {o_term, c.term.data(), c.term.size() * 4},
-                  {o_out, c.outids.data(), c.outids.size() * 4}};
+                  {o_out, c.outids.data(), c.outids.size() * 4},
+                  {o_pbytes, c.pat_bytes.data(), c.pat_bytes.size()},
+                  {o_poff, c.pat_off.data(), c.pat_off.size() * 8},
+                  {o_plen, c.pat_len.data(), c.pat_len.size() * 4}};
     for (const Piece &p : pieces) {
         if (!p.n) continue;
         e = hipMemcpy(b + p.off, p.src, p.n, hipMemcpyHostToDevice);
@@ -121,6 +129,10 @@ int upload(glop_dict *h) {
     d.probe_bits = c.probe_bits;
     d.tile_kib = c.tile_kib;
     d.filter = c.filter;
+    d.verify_from = c.verifies() ? c.prefix_len : 0u;
+    d.pat_bytes = c.verifies() ? b + o_pbytes : nullptr;
+    d.pat_off = c.verifies() ? reinterpret_cast<const uint64_t *>(b + o_poff) : nullptr;
+    d.pat_len = c.verifies() ? reinterpret_cast<const uint32_t *>(b + o_plen) : nullptr;
     return GLOP_OK;
 }
 
@@ -536,6 +548,114 @@ int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_
     return ok();
 }
 
+int glop_match_host(glop_handle_t h, const uint8_t *h_text, uint64_t len, glop_match_t *d_out,
+                    uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, uint64_t chunk_bytes,
+                    void *stream) {
+    int rc = check_match_args(h, h_text, len, d_out, max_matches, d_counts);
+    if (rc != GLOP_OK) return rc;
+    rc = check_device(h);
+    if (rc != GLOP_OK) return rc;
+    const uint64_t chunk = chunk_bytes ? chunk_bytes : (64ull << 20);
+    if (chunk < 4096) return fail(GLOP_EINVAL, "chunk_bytes must be at least 4096");
+    const uint64_t halo = h->c.max_len ? h->c.max_len - 1 : 0;
+    const uint64_t piece_max = std::min<uint64_t>(len, chunk + halo);
+    const uint64_t npieces = len ? (len + chunk - 1) / chunk : 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // Resources of the call, released on every path.
+    struct Res {
+        uint8_t *pinned[2] = {nullptr, nullptr};
+        uint8_t *dev = nullptr;  // two piece buffers | workspace | two running-total words
+        hipStream_t copy = nullptr;
+        hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
+        ~Res() {
+            for (int b = 0; b < 2; ++b) {
+                if (copied[b]) (void)hipEventDestroy(copied[b]);
+                if (consumed[b]) (void)hipEventDestroy(consumed[b]);
+                if (pinned[b]) (void)hipHostFree(pinned[b]);
+            }
+            if (copy) (void)hipStreamDestroy(copy);
+            if (dev) (void)hipFree(dev);
+        }
+    } r;
+    const uint64_t buf = align256(std::max<uint64_t>(piece_max, 16));
+    const uint64_t ws_bytes = glop::workspace_bytes(piece_max, h->num_cus);
+    const uint64_t o_ws = 2 * buf, o_cursor = o_ws + align256(ws_bytes);
+    hipError_t e;
+    if ((e = hipMalloc((void **)&r.dev, o_cursor + 256)) != hipSuccess)
+        return fail(GLOP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipHostMalloc((void **)&r.pinned[b], buf, hipHostMallocDefault)) != hipSuccess)
+            return fail(GLOP_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        if ((e = hipEventCreateWithFlags(&r.copied[b], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&r.consumed[b], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+    }
+    if ((e = hipStreamCreateWithFlags(&r.copy, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    uint64_t *cursor = reinterpret_cast<uint64_t *>(r.dev + o_cursor);  // two words, used in turn
+    // A text already in pinned host memory is uploaded from where it is.
+    bool src_pinned = false;
+    if (len) {
+        hipPointerAttribute_t attr{};
+        src_pinned = hipPointerGetAttributes(&attr, h_text) == hipSuccess && attr.type == hipMemoryTypeHost;
+        (void)hipGetLastError();  // a pageable pointer leaves an error behind; clear it
+    }
+    const unsigned hw = std::thread::hardware_concurrency();
+    const unsigned nthreads = std::max(1u, std::min(8u, hw ? hw : 1u));
+    auto stage = [&](uint8_t *dst, const uint8_t *src, uint64_t n) {
+        // Pageable to pinned, split over host threads (one pass of host memory bandwidth).
+        const uint64_t per = (n + nthreads - 1) / nthreads;
+        std::vector<std::thread> ts;
+        for (unsigned t = 1; t < nthreads && per * t < n; ++t)
+            ts.emplace_back([=] { std::memcpy(dst + per * t, src + per * t, std::min(per, n - per * t)); });
+        std::memcpy(dst, src, std::min(per, n));
+        for (auto &t : ts) t.join();
+    };
+    for (uint64_t k = 0; k < npieces; ++k) {
+        const int b = (int)(k & 1);
+        const uint64_t start = k * chunk;
+        const uint64_t starts = len ? std::min(chunk, len - start) : 0;
+        const uint64_t bytes = len ? std::min(chunk + halo, len - start) : 0;
+        uint8_t *dbuf = r.dev + (uint64_t)b * buf;
+        if (bytes) {
+            const uint8_t *src = h_text + start;
+            if (!src_pinned) {
+                if (k >= 2 && (e = hipEventSynchronize(r.copied[b])) != hipSuccess) return hip_fail(e, "staging wait");
+                stage(r.pinned[b], src, bytes);
+                src = r.pinned[b];
+            }
+            if (k >= 2 && (e = hipStreamWaitEvent(r.copy, r.consumed[b], 0)) != hipSuccess)
+                return hip_fail(e, "hipStreamWaitEvent");
+            if ((e = hipMemcpyAsync(dbuf, src, bytes, hipMemcpyHostToDevice, r.copy)) != hipSuccess ||
+                (e = hipEventRecord(r.copied[b], r.copy)) != hipSuccess ||
+                (e = hipStreamWaitEvent(s, r.copied[b], 0)) != hipSuccess)
+                return hip_fail(e, "piece upload");
+        }
+        glop::MatchLaunch a{};
+        a.d = h->dd;
+        a.text = bytes ? dbuf : nullptr;
+        a.len = bytes;
+        a.out = d_out;
+        a.max_matches = max_matches;
+        a.counts = d_counts;
+        a.total = cursor + ((k + 1) & 1);
+        a.workspace = r.dev + o_ws;
+        a.workspace_bytes = ws_bytes;
+        a.num_cus = h->num_cus;
+        a.start_limit = starts;
+        a.base_in = k ? cursor + (k & 1) : nullptr;
+        a.offset_add = start;
+        a.accumulate = k > 0;
+        if ((e = glop::launch_match(a, s)) != hipSuccess) return hip_fail(e, "kernel launch");
+        if ((e = hipEventRecord(r.consumed[b], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    if (d_total && (e = hipMemcpyAsync(d_total, cursor + (npieces & 1), 8, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(e, "total copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ok();
+}
+
 uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t max_total_bytes) {
     if (!h) {
         fail(GLOP_EINVAL, "NULL handle");
@@ -606,6 +726,8 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->probe_bits = c.probe_bits;
     out->tile_kib = c.tile_kib;
     out->filter_keys = c.filter_keys;
+    out->prefix_len = c.prefix_len;
+    out->candidates = c.candidates;
     out->device_bytes = h->blob_bytes;
     out->device = h->blob ? h->device : -1;
     return ok();

@@ -100,7 +100,7 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
         const uint32_t n = d.num_patterns;
         const uint32_t blocks = n ? (n + 255) / 256 : 1;
         hipLaunchKernelGGL(glop_zero_kernel<0>, dim3(blocks > 1024 ? 1024 : blocks), dim3(256), 0, stream, a.counts, n,
-                           a.total);
+                           a.total, a.base_in, a.accumulate ? 0u : 1u);
         hipError_t e = hipGetLastError();
         if (a.events && a.events->scan_end) (void)hipEventRecord((hipEvent_t)a.events->scan_end, stream);
         if (a.events && a.events->emit_end) (void)hipEventRecord((hipEvent_t)a.events->emit_end, stream);
@@ -110,6 +110,9 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     const Geometry g = geometry(a.len, a.num_cus, tile);
     ScanParams P = base_params(d, a.counts);
     P.one = make_span(a.text, a.len, d.min_len);
+    if (a.start_limit && a.start_limit < a.len && P.one.head + a.start_limit < P.one.valid_end)
+        P.one.valid_end = P.one.head + a.start_limit;
+    P.zero_counts = a.accumulate ? 0u : 1u;
     P.ntiles = g.ntiles;
     P.tiles_per_item = g.tiles_per_item;
     uint8_t *ws = static_cast<uint8_t *>(a.workspace);
@@ -117,7 +120,7 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     P.tile_nm = reinterpret_cast<uint32_t *>(ws + g.off_nm);
     P.staging = reinterpret_cast<uint64_t *>(ws + g.off_stage);
     P.itemsum = reinterpret_cast<uint64_t *>(ws + g.off_item);
-    const EmitParams E{a.out, a.max_matches, a.total, nullptr};
+    const EmitParams E{a.out, a.max_matches, a.total, nullptr, a.base_in, a.offset_add};
     return variant_for(d).one(P, E, g.grid, stream, a.events);
 }
 
@@ -138,7 +141,7 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.tile_start = reinterpret_cast<uint64_t *>(ws + g.off_start);
     P.itemsum = reinterpret_cast<uint64_t *>(ws + g.off_item);
     P.meta = reinterpret_cast<uint64_t *>(ws + g.off_meta);
-    const EmitParams E{reinterpret_cast<glop_match_t *>(a.out), a.max_matches, nullptr, a.chunk_first};
+    const EmitParams E{reinterpret_cast<glop_match_t *>(a.out), a.max_matches, nullptr, a.chunk_first, nullptr, 0};
     return variant_for(d).batch(P, E, a.chunk_count, a.total, a.num_cus, stream);
 }
 

@@ -20,6 +20,11 @@ struct MatchLaunch {
     uint64_t workspace_bytes;
     int num_cus;
     const glop_events_t *events;  // may be null
+    // A text matched in consecutive pieces (each piece one call on one stream):
+    uint64_t start_limit;         // only starts below this offset of the piece (0 = all)
+    const uint64_t *base_in;      // device word: records of earlier pieces (null = 0); not `total`
+    uint64_t offset_add;          // the piece's offset in the whole text
+    bool accumulate;              // add to the counts instead of clearing them first
 };
 
 struct BatchLaunch {

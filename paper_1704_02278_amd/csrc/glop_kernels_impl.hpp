@@ -133,13 +133,16 @@ struct ScanParams {
     uint64_t *staging;           // kStageCap per tile: (offset in tile << 32) | state
     uint64_t *itemsum;           // records per work item
     uint64_t *counts;            // per-pattern counts
+    uint32_t zero_counts;        // single text: the scan kernel clears the counts first
 };
 
 struct EmitParams {
-    glop_match_t *out;     // (offset, id, chunk) records; glop_batch_match_t has this layout
+    glop_match_t *out;       // (offset, id, chunk) records; glop_batch_match_t has this layout
     uint64_t max_matches;
-    uint64_t *total;       // single text (may be null)
-    uint64_t *chunk_first; // batch
+    uint64_t *total;         // single text (may be null): records before this call plus its own
+    uint64_t *chunk_first;   // batch
+    const uint64_t *base_in; // single text: device word with the records before this call, or null (0)
+    uint64_t offset_add;     // single text: added to every record's offset
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
@@ -325,6 +328,29 @@ __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, co
     return last;
 }
 
+// Verify stage of a truncated trie (Sections 2 and 5 complete a truncated
+// match by comparing the rest of the pattern): listed pattern id matches at
+// coordinate x only if its bytes [verify_from, len) follow in the text.
+__device__ __forceinline__ bool verified(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t id) {
+    const uint32_t len = d.pat_len[id];
+    if (len <= d.verify_from) return true;
+    if (x + len > s.span_end) return false;
+    const uint8_t *p = d.pat_bytes + d.pat_off[id];
+    for (uint32_t k = d.verify_from; k < len; ++k)
+        if (s.abase[x + k] != p[k]) return false;
+    return true;
+}
+
+// Records at coordinate x of a walk whose deepest terminal is st.
+__device__ __forceinline__ uint32_t state_records(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t st) {
+    const uint32_t cnt = d.term[2 * st + 1];
+    if (!d.verify_from) return cnt;
+    const uint32_t first = d.term[2 * st];
+    uint32_t n = 0;
+    for (uint32_t k = 0; k < cnt; ++k) n += verified(d, s, x, d.outids[first + k]) ? 1u : 0u;
+    return n;
+}
+
 // Where tile t lies: its text (or chunk), its first coordinate, and whether
 // every byte it loads is inside that text.
 struct TileInfo {
@@ -387,15 +413,16 @@ struct StageSink {
     __device__ __forceinline__ StageSink(uint32_t *nm_, uint64_t *rec_, uint64_t tb_)
         : nm_l(nm_), rec_l(rec_), tb(tb_) {}
 
-    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, const TileInfo &, uint32_t off,
+    __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
-        const bool m = last != 0;
+        const uint32_t cnt = last ? state_records(P.d, ti.s, ti.x0 + off, last) : 0u;
+        const bool m = cnt != 0;
         const uint64_t bal = __ballot(m);
         if (bal == 0) return;
         const uint32_t pos = nm + (uint32_t)__popcll(bal & lanemask_lt());
         if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = ((uint64_t)off << 32) | last;
         nm += (uint32_t)__popcll(bal);
-        rec += wave_sum_u32(m ? P.d.term[2 * last + 1] : 0u);
+        rec += wave_sum_u32(cnt);
     }
     __device__ __forceinline__ void finish(uint64_t t) {
         if (lane_id() == 0) {
@@ -415,17 +442,20 @@ struct DirectSink {
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
-        const bool m = last != 0;
+        const uint64_t x = ti.x0 + off;
+        const uint32_t cnt = last ? state_records(P.d, ti.s, x, last) : 0u;
+        const bool m = cnt != 0;
         if (__ballot(m) == 0) return;
-        const uint32_t first = m ? P.d.term[2 * last] : 0u;
-        const uint32_t cnt = m ? P.d.term[2 * last + 1] : 0u;
         uint32_t tot;
         const uint32_t excl = wave_excl_scan_u32(cnt, tot);
         if (m) {
-            const uint64_t i = ti.x0 + off - ti.s.head;
-            for (uint32_t k = 0; k < cnt; ++k) {
+            const uint64_t i = x - ti.s.head + E->offset_add;
+            const uint32_t first = P.d.term[2 * last], listed = P.d.term[2 * last + 1];
+            uint32_t j = 0;
+            for (uint32_t k = 0; k < listed; ++k) {
                 const uint32_t id = P.d.outids[first + k];
-                const uint64_t pos = base + cursor + excl + k;
+                if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
+                const uint64_t pos = base + cursor + excl + j++;
                 if (pos < E->max_matches) E->out[pos] = glop_match_t{i, id, ti.chunk};
                 atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
             }
@@ -600,16 +630,19 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
     const uint32_t t_rel = ent >> kPosBits;
     const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
     const uint64_t t = tb + t_rel;
-    uint32_t last = 0;
+    uint32_t last = 0, nrec = 0;
     if (act) {
         const TileInfo ti = tile_info<BATCH, TILE>(P, t);
         const uint64_t x = ti.x0 + (int64_t)off;
-        if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) last = walk(P.d, ti.s, cls, x);
+        if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) {
+            last = walk(P.d, ti.s, cls, x);
+            if (last) nrec = state_records(P.d, ti.s, x, last);
+        }
     }
-    if (last) {
+    if (nrec) {
         const uint32_t slot = atomicAdd(&nm_l[t_rel], 1u);
         if (slot < kStageCap) P.staging[t * kStageCap + slot] = ((uint64_t)off << 32) | last;
-        atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)P.d.term[2 * last + 1]);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)nrec);
     }
 }
 
@@ -765,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
 
     // One text: the emit kernel adds into the counts after this kernel ends.
     // (A batch's prep kernel zeroes them.)
-    if (!BATCH)
+    if (!BATCH && P.zero_counts)
         for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < P.d.num_patterns;
              k += (uint64_t)gridDim.x * kBlock)
             P.counts[k] = 0;
@@ -867,7 +900,13 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
     bool staged = false, has_last = false;
     uint64_t last_total = 0;
-    if (threadIdx.x == 0) any_failed = any_over = 0;
+    // Records written by earlier calls into the same output (a text matched
+    // in consecutive pieces); read before any workgroup can write the total.
+    const uint64_t call_base = (!BATCH && E.base_in) ? *E.base_in : 0ull;
+    if (threadIdx.x == 0) {
+        any_failed = call_base == kItemFailed ? 1u : 0u;  // an earlier piece failed
+        any_over = 0;
+    }
     __syncthreads();
 
     // Thread-0 steps inside the loop sit between barriers of the same item
@@ -889,7 +928,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         uint32_t over = 0;
         for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
         if (over) atomicOr(&any_over, 1u);
-        uint64_t base = block_sum_u64(part, red);  // its barriers publish any_over
+        uint64_t base = call_base + block_sum_u64(part, red);  // its barriers publish any_over
         if (any_over && !staged) {
             stage_tables<FILTER>(P, bm, cls);
             staged = true;
@@ -926,12 +965,15 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                         }
                         prev = ent;
                         const uint32_t st = (uint32_t)ent;
-                        const uint64_t i = ti.x0 + (ent >> 32) - ti.s.head;
+                        const uint64_t x = ti.x0 + (ent >> 32);
+                        const uint64_t i = x - ti.s.head + E.offset_add;
                         const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
-                        for (uint32_t k = 0; k < cnt; ++k, ++pos) {
+                        for (uint32_t k = 0; k < cnt; ++k) {
                             const uint32_t id = P.d.outids[first + k];
+                            if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
                             if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
                             atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                            ++pos;
                         }
                     }
                 }
@@ -964,10 +1006,14 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     }
 }
 
+// A call with nothing to match: clear the counts (unless they accumulate over
+// consecutive pieces) and carry the running record total.
 template <int = 0>
-__global__ void glop_zero_kernel(uint64_t *counts, uint32_t n, uint64_t *total) {
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) counts[k] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0;
+__global__ void glop_zero_kernel(uint64_t *counts, uint32_t n, uint64_t *total, const uint64_t *base_in,
+                                 uint32_t zero_counts) {
+    if (zero_counts)
+        for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) counts[k] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && total) *total = base_in ? *base_in : 0ull;
 }
 
 // Batch prep (one workgroup): tiles per chunk -> first tile of each chunk,

@@ -61,4 +61,10 @@ struct GlopDevDict {
     uint32_t min_len, max_len;
     uint32_t qgram, qmask, stride, bitmap_log2, probe_bits, tile_kib;
     int32_t filter;  // GLOP_FILTER_NONE or GLOP_FILTER_QGRAM
+    // Truncated trie with verification: a terminal's listed pattern j is a
+    // match only if bytes [verify_from, len_j) of the text also equal it.
+    uint32_t verify_from;      // 0 = every listed pattern matches (no verify stage)
+    const uint8_t *pat_bytes;  // all patterns back to back
+    const uint64_t *pat_off;   // first byte of pattern j in pat_bytes
+    const uint32_t *pat_len;   // length of pattern j
 };

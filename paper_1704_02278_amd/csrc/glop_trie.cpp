@@ -129,10 +129,18 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
         err = "NULL pattern or length array";
         return GLOP_EINVAL;
     }
+    if (o.prefix_len > 255 || (o.candidates && !o.prefix_len)) {
+        err = "prefix_len must be 0..255, and candidates needs prefix_len";
+        return GLOP_EINVAL;
+    }
     c = Compiled{};
     c.num_patterns = n;
+    c.prefix_len = o.prefix_len;
+    c.candidates = o.candidates ? 1u : 0u;
     c.min_len = n ? 0xFFFFFFFFu : 0;
     bool used[256] = {};
+    // Bytes of pattern j the trie holds (all of it, or its first prefix_len).
+    auto trie_len = [&](uint32_t j) { return c.prefix_len ? std::min(c.prefix_len, lengths[j]) : lengths[j]; };
     for (uint32_t j = 0; j < n; ++j) {
         if (lengths[j] == 0) {
             err = "pattern " + std::to_string(j) + " is empty";
@@ -146,9 +154,12 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             err = "pattern " + std::to_string(j) + " is NULL";
             return GLOP_EINVAL;
         }
-        c.min_len = std::min(c.min_len, lengths[j]);
+        // min_len bounds where a trie match can start (the filter and the
+        // valid starts use it); max_len is the longest full pattern (the
+        // overlap a split text needs, and how far verification reads).
+        c.min_len = std::min(c.min_len, trie_len(j));
         c.max_len = std::max(c.max_len, lengths[j]);
-        for (uint32_t k = 0; k < lengths[j]; ++k) used[patterns[j][k]] = true;
+        for (uint32_t k = 0; k < trie_len(j); ++k) used[patterns[j][k]] = true;
     }
     if (o.filter != GLOP_FILTER_AUTO && o.filter != GLOP_FILTER_NONE && o.filter != GLOP_FILTER_QGRAM) {
         err = "unknown filter option";
@@ -168,7 +179,7 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
         uint64_t S = 1;
         for (uint32_t j = 0; j < n; ++j) {
             uint64_t s = 0;
-            for (uint32_t k = 0; k < lengths[j]; ++k) {
+            for (uint32_t k = 0; k < trie_len(j); ++k) {
                 uint64_t idx = s * C + c.cls[patterns[j][k]];
                 uint32_t nx = rows[idx];
                 if (nx == 0) {
@@ -251,6 +262,19 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             }
         }
 
+        if (c.verifies()) {
+            c.pat_off.resize(n);
+            c.pat_len.resize(n);
+            uint64_t total = 0;
+            for (uint32_t j = 0; j < n; ++j) {
+                c.pat_off[j] = total;
+                c.pat_len[j] = lengths[j];
+                total += lengths[j];
+            }
+            c.pat_bytes.resize(total);
+            for (uint32_t j = 0; j < n; ++j) std::memcpy(c.pat_bytes.data() + c.pat_off[j], patterns[j], lengths[j]);
+        }
+
         const int rc = build_filter(patterns, n, o, c, err);
         if (rc != GLOP_OK) return rc;
     } catch (const std::bad_alloc &) {
@@ -310,6 +334,12 @@ int cpu_walk(const Compiled &c, const uint8_t *text, uint64_t len, glop_match_t 
                 uint32_t first = c.term[2 * f.state], cnt = c.term[2 * f.state + 1];
                 for (uint32_t k = 0; k < cnt; ++k) {
                     uint32_t id = c.outids[first + k];
+                    if (c.verifies() && c.pat_len[id] > c.prefix_len) {
+                        const uint32_t L = c.pat_len[id], P = c.prefix_len;
+                        if (f.offset + L > len ||
+                            std::memcmp(text + f.offset + P, c.pat_bytes.data() + c.pat_off[id] + P, L - P) != 0)
+                            continue;
+                    }
                     counts[id] += 1;
                     if (emitted < max_matches) out[emitted] = glop_match_t{f.offset, id, 0};
                     ++emitted;
