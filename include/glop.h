@@ -329,8 +329,9 @@ uint32_t glop_max_len(glop_handle_t h);
  * arrive.  A scheduler thread forms batches continuously: whenever one of its
  * stream slots is free it takes the dictionary whose oldest waiting request
  * arrived first and packs that dictionary's waiting requests, oldest first,
- * into one glop_match_batch launch, up to max_batch_requests requests and
- * max_batch_bytes bytes, and as far as the HBM budget allows.  Requests that
+ * into one glop_match_batch launch (a lone request takes the single-text
+ * kernels), up to max_batch_requests requests and max_batch_bytes bytes, and
+ * as far as the HBM budget allows.  Requests that
  * arrive while batches run join the next launch.  The paper streams batches
  * of logs through the device so transfers overlap matching (Section 6) and
  * names real-time operation as future work (Section 8); this is that
@@ -362,7 +363,7 @@ typedef struct glop_server *glop_server_t;
 
 typedef struct {
     int32_t mode;                /* GLOP_SERVE_BATCHED or GLOP_SERVE_PLAIN */
-    uint32_t max_inflight;       /* batches in flight at once (stream slots); 0 = 2 */
+    uint32_t max_inflight;       /* batches in flight at once (stream slots); 0 = 8 */
     uint32_t max_batch_requests; /* 0 = 4096 */
     uint64_t max_batch_bytes;    /* 0 = 1 GiB */
     uint64_t hbm_budget_bytes;   /* 0 = 4 GiB */

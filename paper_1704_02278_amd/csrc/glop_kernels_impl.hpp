@@ -67,8 +67,10 @@ constexpr uint32_t kRing4 = 512;
 constexpr uint32_t kHitCap = 8192;
 constexpr uint32_t kHitFree = 0xFFFFFFFFu;
 constexpr uint32_t kPosBits = 15;
-// Tiles per work item at most (per-tile result counters live in LDS).
+// Tiles per work item at most (per-tile result counters live in LDS), and at
+// least for a batch (one tile per wave).
 constexpr uint32_t kMaxTilesPerItem = 512;
+constexpr uint32_t kMinBatchTilesPerItem = 16;
 
 // Batch metadata words in the workspace.
 enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaError = 5, kMetaWords = 8 };
@@ -1117,7 +1119,7 @@ struct BatchGeometry {
 inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) {
     BatchGeometry g{};
     g.tile_cap = (max_total_bytes + 16ull * nchunks) / kMinTileBytes + nchunks + 1;
-    g.item_cap = (g.tile_cap + kMaxTilesPerItem - 1) / kMaxTilesPerItem;
+    g.item_cap = (g.tile_cap + kMinBatchTilesPerItem - 1) / kMinBatchTilesPerItem;
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.tile_cap * 8);
     g.off_stage = align256(g.off_nm + g.tile_cap * 4);
@@ -1167,7 +1169,11 @@ struct Kernels {
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
         const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
-        const uint32_t cus = (uint32_t)(num_cus > 0 ? num_cus : 1);
+        // Persistent workgroups: one per CU, fewer if the batch has fewer items.
+        uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);
+        const uint64_t items = (P.tile_cap + P.tiles_per_item - 1) / P.tiles_per_item;
+        if (items < wg) wg = items ? items : 1;
+        const uint32_t cus = (uint32_t)wg;
         hipLaunchKernelGGL((glop_batch_prep_kernel<R * kRoundBytes>), dim3(1), dim3(kBlock), 0, s, P);
         hipError_t e;
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -58,16 +58,15 @@ struct Inflight {
     int64_t launch_ns = 0;
     hipEvent_t done = nullptr;
     int slot = -1;
+    bool single = false;  // one request, matched with the single-text kernels
 };
 
-// Stream slot: a stream, its completion event and pinned result words.
+// Stream slot: a stream, its completion event and pinned words.
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     glop_chunk_t *h_table = nullptr;  // pinned, max_batch_requests entries
-    uint64_t *h_first = nullptr;      // pinned
-    uint64_t *h_count = nullptr;      // pinned
-    uint64_t *h_total = nullptr;      // pinned, one word
+    uint64_t *h_res = nullptr;        // pinned: first[n] | count[n] | total, copied back in one piece
     bool busy = false;
 };
 
@@ -146,12 +145,12 @@ struct glop_server {
                 c.tag = r.tag;
                 c.dict = r.dict;
                 uint64_t first = 0, count = 0;
-                if (o.mode == GLOP_SERVE_PLAIN) {
-                    count = sl.h_total[i];
+                if (f.single) {
+                    count = sl.h_res[0];
                 } else {
-                    first = sl.h_first[i];
-                    count = sl.h_count[i];
-                    if (*sl.h_total == ~0ull) set_error(GLOP_EINTERNAL, "batch workspace overflow");
+                    first = sl.h_res[i];
+                    count = sl.h_res[nreq + i];
+                    if (sl.h_res[2 * nreq] == ~0ull) set_error(GLOP_EINTERNAL, "batch workspace overflow");
                 }
                 c.matches = count;
                 c.records = first >= f.cap ? 0 : std::min<uint64_t>(count, f.cap - first);
@@ -221,17 +220,19 @@ struct glop_server {
         }
         if (n == 0) return false;  // the oldest request waits for memory
         Slot &sl = slots[si];
+        if (n == 1) return launch_single_locked(si, q.front(), dict, &q);
         const uint64_t own = batch_own(dict, n, bytes);
-        const uint64_t o_table = 0, o_first = align256((uint64_t)n * 16), o_count = o_first + align256((uint64_t)n * 8);
-        const uint64_t o_counts = o_count + align256((uint64_t)n * 8);
-        const uint64_t o_total = o_counts + align256((uint64_t)npat[dict] * 8);
-        const uint64_t o_ws = o_total + 256;
+        // Device block: table | first[n] count[n] total (one copy back) | counts | workspace | records.
+        const uint64_t o_table = 0, o_res = align256((uint64_t)n * 16);
+        const uint64_t o_counts = o_res + align256((2ull * n + 1) * 8);
+        const uint64_t o_ws = o_counts + align256((uint64_t)npat[dict] * 8);
         const uint64_t ws_bytes = glop_batch_workspace_bytes(dicts[dict], n, bytes);
         const uint64_t o_out = o_ws + align256(ws_bytes);
         const uint64_t dev_bytes = o_out + cap * 16;
         std::shared_ptr<Block> blk;
         if (!alloc_block(sl, dev_bytes, own, n, blk)) return false;
         uint8_t *b = static_cast<uint8_t *>(blk->dev);
+        uint64_t *res = reinterpret_cast<uint64_t *>(b + o_res);
         Inflight f;
         f.reqs.assign(q.begin(), q.begin() + n);
         q.erase(q.begin(), q.begin() + n);
@@ -252,16 +253,11 @@ struct glop_server {
         int rc = e == hipSuccess ? GLOP_OK : GLOP_EHIP;
         if (rc == GLOP_OK)
             rc = glop_match_batch(dicts[dict], reinterpret_cast<const glop_chunk_t *>(b + o_table), n, bytes,
-                                  reinterpret_cast<glop_batch_match_t *>(f.out), cap,
-                                  reinterpret_cast<uint64_t *>(b + o_first), reinterpret_cast<uint64_t *>(b + o_count),
-                                  reinterpret_cast<uint64_t *>(b + o_counts), reinterpret_cast<uint64_t *>(b + o_total),
-                                  b + o_ws, ws_bytes, sl.stream);
+                                  reinterpret_cast<glop_batch_match_t *>(f.out), cap, res, res + n,
+                                  reinterpret_cast<uint64_t *>(b + o_counts), res + 2 * n, b + o_ws, ws_bytes,
+                                  sl.stream);
         if (rc == GLOP_OK &&
-            ((e = hipMemcpyAsync(sl.h_first, b + o_first, (uint64_t)n * 8, hipMemcpyDeviceToHost, sl.stream)) !=
-                 hipSuccess ||
-             (e = hipMemcpyAsync(sl.h_count, b + o_count, (uint64_t)n * 8, hipMemcpyDeviceToHost, sl.stream)) !=
-                 hipSuccess ||
-             (e = hipMemcpyAsync(sl.h_total, b + o_total, 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
+            ((e = hipMemcpyAsync(sl.h_res, res, (2ull * n + 1) * 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
              (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess))
             rc = GLOP_EHIP;
         if (rc != GLOP_OK) set_error(rc, std::string("batch launch failed: ") + glop_last_error_message());
@@ -270,18 +266,15 @@ struct glop_server {
         return true;
     }
 
-    // Plain mode: every request alone, in arrival order, on slot 0's stream.
-    bool launch_plain_locked() {
-        if (fifo.empty()) return false;
-        const int si = free_slot_locked();
-        if (si < 0) return false;
-        const Request &r0 = fifo.front();
-        const uint64_t need = request_need(r0.len), own = plain_own(r0.dict, r0.len);
+    // One request with the single-text kernels (glop_match_ws) on slot si;
+    // `from` is the queue it is taken from (its front).
+    bool launch_single_locked(int si, const Request &r0, uint32_t dict, std::deque<Request> *from) {
+        const uint64_t need = request_need(r0.len), own = plain_own(dict, r0.len);
         if (reserved + need + own > o.hbm_budget_bytes) return false;
         Slot &sl = slots[si];
-        const uint32_t np = npat[r0.dict];
+        const uint32_t np = npat[dict];
         const uint64_t o_counts = 0, o_total = align256((uint64_t)np * 8), o_ws = o_total + 256;
-        const uint64_t ws_bytes = glop_workspace_bytes(dicts[r0.dict], r0.len);
+        const uint64_t ws_bytes = glop_workspace_bytes(dicts[dict], r0.len);
         const uint64_t cap = out_capacity(r0.len);
         const uint64_t o_out = o_ws + align256(ws_bytes);
         std::shared_ptr<Block> blk;
@@ -289,7 +282,7 @@ struct glop_server {
         uint8_t *b = static_cast<uint8_t *>(blk->dev);
         Inflight f;
         f.reqs.push_back(r0);
-        fifo.pop_front();
+        from->pop_front();
         f.reqs[0].reserved = need;
         reserved += need + own;
         f.block = blk;
@@ -297,19 +290,29 @@ struct glop_server {
         f.cap = cap;
         f.slot = si;
         f.done = sl.done;
+        f.single = true;
         f.launch_ns = now_ns();
-        int rc = glop_match_ws(dicts[r0.dict], r0.len ? r0.text : nullptr, r0.len, f.out, cap,
+        const Request &r = f.reqs[0];
+        int rc = glop_match_ws(dicts[dict], r.len ? r.text : nullptr, r.len, f.out, cap,
                                reinterpret_cast<uint64_t *>(b + o_counts), reinterpret_cast<uint64_t *>(b + o_total),
                                b + o_ws, ws_bytes, sl.stream, nullptr);
         hipError_t e = hipSuccess;
         if (rc == GLOP_OK &&
-            ((e = hipMemcpyAsync(sl.h_total, b + o_total, 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
+            ((e = hipMemcpyAsync(sl.h_res, b + o_total, 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
              (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess))
             rc = GLOP_EHIP;
-        if (rc != GLOP_OK) set_error(rc, std::string("plain launch failed: ") + glop_last_error_message());
+        if (rc != GLOP_OK) set_error(rc, std::string("launch failed: ") + glop_last_error_message());
         sl.busy = true;
         inflight.push_back(std::move(f));
         return true;
+    }
+
+    // Plain mode: every request alone, in arrival order, on one stream.
+    bool launch_plain_locked() {
+        if (fifo.empty()) return false;
+        const int si = free_slot_locked();
+        if (si < 0) return false;
+        return launch_single_locked(si, fifo.front(), fifo.front().dict, &fifo);
     }
 
     void release_held_locked(uint64_t id) {
@@ -379,7 +382,7 @@ glop_server_t glop_server_create(const glop_server_opts *opts) {
     glop_server_opts &o = s->o;
     if (o.mode != GLOP_SERVE_BATCHED && o.mode != GLOP_SERVE_PLAIN)
         return create_fail(s, GLOP_EINVAL, "mode must be GLOP_SERVE_BATCHED or GLOP_SERVE_PLAIN");
-    if (!o.max_inflight) o.max_inflight = 2;
+    if (!o.max_inflight) o.max_inflight = 8;
     if (!o.max_batch_requests) o.max_batch_requests = 4096;
     if (!o.max_batch_bytes) o.max_batch_bytes = 1ull << 30;
     if (!o.hbm_budget_bytes) o.hbm_budget_bytes = 4ull << 30;
@@ -403,9 +406,7 @@ glop_server_t glop_server_create(const glop_server_opts *opts) {
             return create_fail(s, GLOP_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
         const uint64_t n = o.max_batch_requests;
         if (hipHostMalloc((void **)&sl.h_table, n * sizeof(glop_chunk_t), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&sl.h_first, n * 8, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&sl.h_count, n * 8, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&sl.h_total, n * 8, hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc((void **)&sl.h_res, (2 * n + 1) * 8, hipHostMallocDefault) != hipSuccess)
             return create_fail(s, GLOP_ENOMEM, "pinned host allocation failed");
     }
     if ((e = hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -434,7 +435,7 @@ int glop_server_submit(glop_server_t s, uint32_t dict, const uint8_t *d_text, ui
     std::lock_guard<std::mutex> lk(s->mu);
     if (dict >= s->dicts.size() || (len > 0 && !d_text)) return GLOP_EINVAL;
     if (s->error != GLOP_OK) return s->error;
-    const uint64_t own = s->o.mode == GLOP_SERVE_PLAIN ? s->plain_own(dict, len) : s->batch_own(dict, 1, len);
+    const uint64_t own = std::max(s->plain_own(dict, len), s->batch_own(dict, 1, len));
     if (s->request_need(len) + own > s->o.hbm_budget_bytes || len > s->o.max_batch_bytes) return GLOP_EINVAL;
     Request r;
     r.id = s->next_id++;
@@ -498,7 +499,7 @@ void glop_server_destroy(glop_server_t s) {
             (void)hipStreamDestroy(sl.stream);
         }
         if (sl.done) (void)hipEventDestroy(sl.done);
-        for (void *p : {(void *)sl.h_table, (void *)sl.h_first, (void *)sl.h_count, (void *)sl.h_total})
+        for (void *p : {(void *)sl.h_table, (void *)sl.h_res})
             if (p) (void)hipHostFree(p);
     }
     if (shared) (void)hipStreamDestroy(shared);
