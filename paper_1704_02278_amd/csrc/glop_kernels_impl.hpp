@@ -330,16 +330,49 @@ __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, co
     return last;
 }
 
+// 8 text bytes at coordinate z (z >= head; the caller masks bytes past the
+// text).  Built from aligned 8-byte blocks; the second block is read only if
+// it holds a text byte, so both lie in pages the text occupies.
+__device__ __forceinline__ uint64_t text_u64(const Span &s, uint64_t z) {
+    const uint64_t a = z & ~7ull;
+    const uint32_t sh = (uint32_t)(z & 7u) * 8u;
+    const uint64_t lo = *reinterpret_cast<const uint64_t *>(s.abase + a);
+    if (!sh) return lo;
+    const uint64_t hi = a + 8 < s.span_end ? *reinterpret_cast<const uint64_t *>(s.abase + a + 8) : 0ull;
+    return (lo >> sh) | (hi << (64u - sh));
+}
+
 // Verify stage of a truncated trie (Sections 2 and 5 complete a truncated
 // match by comparing the rest of the pattern): listed pattern id matches at
-// coordinate x only if its bytes [verify_from, len) follow in the text.
+// coordinate x only if its bytes [verify_from, len) follow in the text.  The
+// comparison runs 8 bytes at a time from the 8-byte boundary at or below
+// verify_from (patterns are stored 8-byte aligned), four words per step with
+// every load issued before the compares.
 __device__ __forceinline__ bool verified(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t id) {
     const uint32_t len = d.pat_len[id];
     if (len <= d.verify_from) return true;
     if (x + len > s.span_end) return false;
-    const uint8_t *p = d.pat_bytes + d.pat_off[id];
-    for (uint32_t k = d.verify_from; k < len; ++k)
-        if (s.abase[x + k] != p[k]) return false;
+    const uint64_t *p = reinterpret_cast<const uint64_t *>(d.pat_bytes + d.pat_off[id]);
+    for (uint32_t k = d.verify_from & ~7u; k < len; k += 32) {
+        uint64_t t[4], q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t b = k + 8u * u;
+            t[u] = b < len ? text_u64(s, x + b) : 0ull;
+            q[u] = b < len ? p[b / 8] : 0ull;
+        }
+        uint64_t diff = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t b = k + 8u * u;
+            if (b < len) {
+                const uint32_t r = len - b;
+                const uint64_t m = r >= 8 ? ~0ull : ((1ull << (8 * r)) - 1ull);
+                diff |= (t[u] ^ q[u]) & m;
+            }
+        }
+        if (diff) return false;
+    }
     return true;
 }
 

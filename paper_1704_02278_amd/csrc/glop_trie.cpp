@@ -263,15 +263,17 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
         }
 
         if (c.verifies()) {
+            // Each pattern starts 8-byte aligned (the GPU verify stage compares
+            // words); the zero padding is never compared.
             c.pat_off.resize(n);
             c.pat_len.resize(n);
             uint64_t total = 0;
             for (uint32_t j = 0; j < n; ++j) {
                 c.pat_off[j] = total;
                 c.pat_len[j] = lengths[j];
-                total += lengths[j];
+                total += (lengths[j] + 7u) & ~7u;
             }
-            c.pat_bytes.resize(total);
+            c.pat_bytes.assign(total, 0);
             for (uint32_t j = 0; j < n; ++j) std::memcpy(c.pat_bytes.data() + c.pat_off[j], patterns[j], lengths[j]);
         }
 
