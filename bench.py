@@ -508,25 +508,31 @@ def main() -> int:
     }
     if copy:
         result["copy_probe"] = copy
-    # The truncated-trie engine (prefix 8 + GPU verify) on the same text: same
-    # records, different walk and verify cost.
-    d8 = glop.Dict(pats, prefix_len=8)
-    for _ in range(args.warmup):
-        d8.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-    assert int(total.item()) == got_total, "prefix-8 engine disagrees with the full trie"
-    a8 = torch.cuda.Event(enable_timing=True)
-    b8 = torch.cuda.Event(enable_timing=True)
-    a8.record(stream)
-    for _ in range(args.steps):
-        d8.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
-    b8.record(stream)
-    torch.cuda.synchronize()
-    ms8 = a8.elapsed_time(b8) / args.steps
-    result["prefix8"] = {"ms_per_step": round(ms8, 5), "GBps": round(n / (ms8 / 1e3) / 1e9, 2),
-                         "vs_full_trie": round(ms_per_step / ms8, 3), "num_states": d8.info()["num_states"],
-                         "engine": "trie of 8-byte prefixes + GPU verify of the rest (exact)"}
-    del d8
+    # Other exact configurations of the same match on the same text: the
+    # truncated-trie engine (prefix 8 + GPU verify) and the blocked filter.
+    def time_dict(dd):
+        for _ in range(args.warmup):
+            dd.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        assert int(total.item()) == got_total, "configurations disagree on the match count"
+        a_ = torch.cuda.Event(enable_timing=True)
+        b_ = torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        for _ in range(args.steps):
+            dd.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
+        b_.record(stream)
+        torch.cuda.synchronize()
+        return a_.elapsed_time(b_) / args.steps
+
+    for key, opts, what in (("prefix8", dict(prefix_len=8), "trie of 8-byte prefixes + GPU verify of the rest"),
+                            ("blocked_filter", dict(probe_bits=3), "two filter bits in one word (one LDS read per probe)"),
+                            ("prefix8_blocked", dict(prefix_len=8, probe_bits=3), "both")):
+        dd = glop.Dict(pats, **opts)
+        ms_alt = time_dict(dd)
+        result[key] = {"ms_per_step": round(ms_alt, 5), "GBps": round(n / (ms_alt / 1e3) / 1e9, 2),
+                       "vs_default": round(ms_per_step / ms_alt, 3), "num_states": dd.info()["num_states"],
+                       "config": what}
+        del dd
 
     if not args.no_host_stream:
         log("[bench] host-streamed input ...")

@@ -83,8 +83,10 @@ typedef struct glop_dict *glop_handle_t;
  *               the shortest pattern length.
  *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
  *               resident in LDS).
- *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram (independent
- *               hashes: a Bloom filter with one or two hash functions).
+ *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram at independent
+ *               positions (a Bloom filter with one or two hash functions), or
+ *               3 = two bits within one 32-bit word chosen by one hash (a
+ *               blocked Bloom filter: one lookup per probe; 8 KiB tiles only).
  *   tile_kib    0 = automatic (8); 8 or 16: bytes of text one wavefront streams
  *               per tile (16 bytes per lane per round, 8 or 16 rounds).  16 is
  *               available with the stride-4 filter only.

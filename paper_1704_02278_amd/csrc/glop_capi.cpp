@@ -442,9 +442,12 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             cand.tile_kib = 8;
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
-        {
+        const uint32_t pb0 = cur.probe_bits;
+        for (uint32_t pb = 1; pb <= 3; ++pb) {
+            if (pb == pb0) continue;
             glop_build_opts cand = cur;
-            cand.probe_bits = cur.probe_bits == 2 ? 1u : 2u;
+            cand.probe_bits = pb;
+            if (pb == 3) cand.tile_kib = 8;
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
         const uint32_t lg0 = cur.bitmap_log2;

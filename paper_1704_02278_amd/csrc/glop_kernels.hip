@@ -18,6 +18,10 @@ GLOP_DECLARE_VARIANT(4, 1, 1, 0, 16)
 GLOP_DECLARE_VARIANT(4, 1, 1, 1, 16)
 GLOP_DECLARE_VARIANT(4, 1, 2, 0, 16)
 GLOP_DECLARE_VARIANT(4, 1, 2, 1, 16)
+GLOP_DECLARE_VARIANT(1, 1, 3, 0, 8)
+GLOP_DECLARE_VARIANT(1, 1, 3, 1, 8)
+GLOP_DECLARE_VARIANT(4, 1, 3, 0, 8)
+GLOP_DECLARE_VARIANT(4, 1, 3, 1, 8)
 
 namespace {
 
@@ -25,6 +29,10 @@ namespace {
 const VariantFns &variant_for(const GlopDevDict &d) {
     if (d.filter != GLOP_FILTER_QGRAM) return GLOP_VARIANT_ID(1, 0, 1, 0, 8)();
     const bool q4 = d.qgram == 4, k2 = d.probe_bits == 2;
+    if (d.probe_bits == 3) {
+        if (d.stride == 4) return q4 ? GLOP_VARIANT_ID(4, 1, 3, 1, 8)() : GLOP_VARIANT_ID(4, 1, 3, 0, 8)();
+        return q4 ? GLOP_VARIANT_ID(1, 1, 3, 1, 8)() : GLOP_VARIANT_ID(1, 1, 3, 0, 8)();
+    }
     if (d.stride == 4) {
         if (d.tile_kib == 16) {
             if (k2) return q4 ? GLOP_VARIANT_ID(4, 1, 2, 1, 16)() : GLOP_VARIANT_ID(4, 1, 2, 0, 16)();
@@ -85,7 +93,9 @@ hipError_t prepare_kernels() {
                                &GLOP_VARIANT_ID(4, 1, 1, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 2, 0, 8)(),
                                &GLOP_VARIANT_ID(4, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 1, 0, 16)(),
                                &GLOP_VARIANT_ID(4, 1, 1, 1, 16)(), &GLOP_VARIANT_ID(4, 1, 2, 0, 16)(),
-                               &GLOP_VARIANT_ID(4, 1, 2, 1, 16)()};
+                               &GLOP_VARIANT_ID(4, 1, 2, 1, 16)(),  &GLOP_VARIANT_ID(1, 1, 3, 0, 8)(),
+                               &GLOP_VARIANT_ID(1, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(4, 1, 3, 0, 8)(),
+                               &GLOP_VARIANT_ID(4, 1, 3, 1, 8)()};
     for (const VariantFns *v : all) {
         const hipError_t e = v->set_lds_limit();
         if (e != hipSuccess) return e;

@@ -271,10 +271,16 @@ __device__ __forceinline__ uint32_t load4(const Span &s, uint64_t x) {
     return keep_bytes(w, (int64_t)x, (int64_t)s.head, (int64_t)s.span_end);
 }
 
-// Bloom probe: 1 if every probe bit of q-gram g is set.
+// Bloom probe: 1 if every probe bit of q-gram g is set.  K = 1 or 2 bits at
+// independent positions; K = 3: two bits in one word (blocked).
 template <int K, bool Q4>
 __device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t sh) {
     if (!Q4) g &= qmask;
+    if (K == 3) {
+        const uint32_t h = glop_hash1(g);
+        const uint32_t m = glop_block_bits(h);
+        return (bm[h >> (sh + 5u)] & m) == m ? 1u : 0u;
+    }
     const uint32_t s1 = glop_hash1(g) >> sh;
     uint32_t hit = bm[s1 >> 5] >> (s1 & 31);
     if (K == 2) {

@@ -49,6 +49,13 @@ GLOP_HD uint32_t glop_hash2(uint32_t g) {
 GLOP_HD uint32_t glop_slot1(uint32_t g, uint32_t bitmap_log2) { return glop_hash1(g) >> (32u - bitmap_log2); }
 GLOP_HD uint32_t glop_slot2(uint32_t g, uint32_t bitmap_log2) { return glop_hash2(g) >> (32u - bitmap_log2); }
 
+// Blocked variant (probe_bits 3): both bits of a q-gram lie in one 32-bit word,
+// so a probe is one hash and one LDS read.  The word comes from the top
+// bitmap_log2 - 5 bits of glop_hash1, the two bit positions from bits 8..12
+// and 13..17 (well mixed by the multiply; the word index uses none of them).
+GLOP_HD uint32_t glop_block_word(uint32_t h, uint32_t bitmap_log2) { return h >> (37u - bitmap_log2); }
+GLOP_HD uint32_t glop_block_bits(uint32_t h) { return (1u << ((h >> 8) & 31u)) | (1u << ((h >> 13) & 31u)); }
+
 struct GlopDevDict {
     const uint32_t *delta;   // num_states * num_classes
     const uint32_t *term;    // 2 * num_states: (first, count) per state

@@ -71,8 +71,12 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
                 return GLOP_EINVAL;
             }
             uint32_t k = o.probe_bits ? o.probe_bits : 2u;
-            if (k != 1 && k != 2) {
-                err = "probe_bits must be 1 or 2";
+            if (k != 1 && k != 2 && k != 3) {
+                err = "probe_bits must be 1, 2 or 3";
+                return GLOP_EINVAL;
+            }
+            if (k == 3 && o.tile_kib == 16) {
+                err = "16 KiB tiles are built for probe_bits 1 and 2";
                 return GLOP_EINVAL;
             }
             c.qgram = q;
@@ -83,6 +87,11 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             c.filter_keys = keys.size();
             c.bitmap.assign((1u << lg) / 32, 0);
             for (uint32_t g : keys) {
+                if (k == 3) {
+                    const uint32_t h = glop_hash1(g);
+                    c.bitmap[glop_block_word(h, lg)] |= glop_block_bits(h);
+                    continue;
+                }
                 const uint32_t s1 = glop_slot1(g, lg);
                 c.bitmap[s1 >> 5] |= 1u << (s1 & 31);
                 if (k == 2) {

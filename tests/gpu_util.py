@@ -24,9 +24,11 @@ def variants_for(patterns):
         out.append(dict(filter=glop.GLOP_FILTER_NONE))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=1))
+        out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=3))
         if minlen >= 7:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=1))
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=3))
         if minlen >= 2:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=1, bitmap_log2=12))
     return out
