@@ -90,16 +90,21 @@ typedef struct glop_dict *glop_handle_t;
  *   tile_kib    0 = automatic (8); 8 or 16: bytes of text one wavefront streams
  *               per tile (16 bytes per lane per round, 8 or 16 rounds).  16 is
  *               available with the stride-4 filter only.
- *   prefix_len  0 = the trie holds the whole patterns; 1..255 = the trie holds
- *               each pattern's first prefix_len bytes only (the library of
- *               Sections 2 and 5 truncates patterns to 8 characters), and a
- *               verify stage on the GPU compares the rest of every candidate
- *               against its full pattern, so the result is still exact.
+ *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;
+ *               1..255 = the trie holds each pattern's first prefix_len bytes
+ *               only (the library of Sections 2 and 5 truncates patterns to 8
+ *               characters), and a verify stage on the GPU compares the rest
+ *               of every candidate against its full pattern, so the result is
+ *               still exact; 0 = automatic: 8 when some pattern is longer than
+ *               8 bytes and no more than 16 patterns share one 8-byte prefix
+ *               (the verify stage then replaces most of each long walk's
+ *               dependent trie steps with a few word compares), else whole.
  *   candidates  with prefix_len: 1 = report the unverified candidates instead,
  *               i.e. every (offset, id) whose first min(prefix_len, length)
  *               bytes match (the truncated matching of Sections 2 and 5, which
  *               can report false positives).  This changes the result.
  */
+#define GLOP_PREFIX_FULL 0xFFFFFFFFu
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1
 #define GLOP_FILTER_QGRAM 2

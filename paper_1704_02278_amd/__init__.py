@@ -34,6 +34,7 @@ GLOP_ENODEV = -5
 GLOP_EINTERNAL = -6
 GLOP_SERVE_BATCHED = 0
 GLOP_SERVE_PLAIN = 1
+GLOP_PREFIX_FULL = 0xFFFFFFFF
 GLOP_FILTER_AUTO = 0
 GLOP_FILTER_NONE = 1
 GLOP_FILTER_QGRAM = 2
@@ -396,7 +397,7 @@ def autotune(patterns, sample, stream=None) -> dict:
     del keep
     o = r.opts
     return {"opts": {"filter": o.filter, "stride": o.stride, "qgram": o.qgram, "bitmap_log2": o.bitmap_log2,
-                     "probe_bits": o.probe_bits, "tile_kib": o.tile_kib},
+                     "probe_bits": o.probe_bits, "tile_kib": o.tile_kib, "prefix_len": o.prefix_len},
             "ms": float(r.ms), "auto_ms": float(r.auto_ms), "evaluated": int(r.evaluated),
             "from_cache": bool(r.from_cache)}
 

@@ -213,7 +213,7 @@ std::string tune_key(const glop_dict *h, uint64_t sample_len) {
     return buf;
 }
 
-// Cache file lines: key TAB filter stride qgram bitmap_log2 probe_bits tile_kib ms auto_ms
+// Cache file lines: key TAB filter stride qgram bitmap_log2 probe_bits tile_kib prefix_len ms auto_ms
 void tune_file_read_locked() {
     if (g_tune_file_read) return;
     g_tune_file_read = true;
@@ -228,10 +228,11 @@ void tune_file_read_locked() {
         *tab = 0;
         glop_tune_result_t r{};
         int filter = 0;
-        unsigned stride = 0, qgram = 0, lg = 0, pb = 0, tile = 0;
-        if (std::sscanf(tab + 1, "%d %u %u %u %u %u %f %f", &filter, &stride, &qgram, &lg, &pb, &tile, &r.ms,
-                        &r.auto_ms) != 8)
+        unsigned stride = 0, qgram = 0, lg = 0, pb = 0, tile = 0, prefix = 0;
+        if (std::sscanf(tab + 1, "%d %u %u %u %u %u %u %f %f", &filter, &stride, &qgram, &lg, &pb, &tile, &prefix,
+                        &r.ms, &r.auto_ms) != 9)
             continue;
+        r.opts.prefix_len = prefix;
         r.opts.filter = filter;
         r.opts.stride = stride;
         r.opts.qgram = qgram;
@@ -248,14 +249,16 @@ void tune_file_append_locked(const std::string &key, const glop_tune_result_t &r
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%d %u %u %u %u %u %.6f %.6f\n", key.c_str(), (int)r.opts.filter, r.opts.stride,
-                 r.opts.qgram, r.opts.bitmap_log2, r.opts.probe_bits, r.opts.tile_kib, r.ms, r.auto_ms);
+    std::fprintf(f, "%s\t%d %u %u %u %u %u %u %.6f %.6f\n", key.c_str(), (int)r.opts.filter, r.opts.stride,
+                 r.opts.qgram, r.opts.bitmap_log2, r.opts.probe_bits, r.opts.tile_kib, r.opts.prefix_len, r.ms,
+                 r.auto_ms);
     std::fclose(f);
 }
 
 // Device buffers and events of one tuning run; released by the destructor.
 struct TuneRun {
-    glop_dict *h = nullptr;
+    glop_dict *h = nullptr;    // the engine being tuned
+    glop_dict *alt = nullptr;  // the other engine (whole patterns vs truncated)
     const uint8_t *const *patterns = nullptr;
     uint32_t n = 0;
     const uint8_t *text = nullptr;
@@ -278,6 +281,7 @@ struct TuneRun {
         for (void *p : {ws, (void *)out, (void *)counts, (void *)total, (void *)bitmap})
             if (p) (void)hipFree(p);
         if (h) glop_free(h);
+        if (alt) glop_free(alt);
     }
 
     int setup() {
@@ -294,10 +298,13 @@ struct TuneRun {
         return GLOP_OK;
     }
 
-    // Time option set o (its free fields are resolved into o); ms = median.
-    int time(glop_build_opts &o, float *ms) {
+    int time(glop_build_opts &o, float *ms) { return time_on(h, o, ms); }
+
+    // Time option set o on handle hd (its free fields are resolved into o,
+    // and o records hd's engine); ms = median.
+    int time_on(glop_dict *hd, glop_build_opts &o, float *ms) {
         glop::Compiled f;
-        f.min_len = h->c.min_len;
+        f.min_len = hd->c.min_len;
         f.num_patterns = n;
         std::string err;
         int rc = glop::build_filter(patterns, n, o, f, err);
@@ -312,11 +319,13 @@ struct TuneRun {
             o.stride = o.qgram = o.bitmap_log2 = o.probe_bits = 0;
         }
         o.tile_kib = f.tile_kib;
+        o.prefix_len = hd->c.prefix_len ? hd->c.prefix_len : GLOP_PREFIX_FULL;
+        o.candidates = 0;
         hipError_t e = hipMemcpyAsync(bitmap, f.bitmap.data(), f.bitmap.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "bitmap upload while tuning");
         glop::MatchLaunch a{};
-        a.d = h->dd;
+        a.d = hd->dd;
         a.d.bitmap = bitmap;
         a.d.filter = f.filter;
         a.d.qgram = f.qgram;
@@ -333,7 +342,7 @@ struct TuneRun {
         a.total = total;
         a.workspace = ws;
         a.workspace_bytes = ws_bytes;
-        a.num_cus = h->num_cus;
+        a.num_cus = hd->num_cus;
         constexpr int kWarm = 2, kTimed = 7;
         float t[kTimed];
         for (int k = 0; k < kWarm + kTimed; ++k) {
@@ -378,6 +387,7 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
     run.s = static_cast<hipStream_t>(stream);
     const glop::Compiled &c = run.h->c;
     glop_build_opts cur{};
+    cur.prefix_len = c.prefix_len ? c.prefix_len : GLOP_PREFIX_FULL;
     cur.filter = c.filter;
     if (c.filter == GLOP_FILTER_QGRAM) {
         cur.stride = c.stride;
@@ -420,8 +430,25 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
         }
         return GLOP_OK;
     };
-    const uint32_t minlen = c.min_len;
+    // Engine: whole patterns or 8-byte prefixes plus verification, each with
+    // its automatic filter options.
+    if (c.max_len > 8) {
+        glop_build_opts eo{};
+        eo.prefix_len = c.prefix_len ? GLOP_PREFIX_FULL : 8u;
+        run.alt = make(patterns, lengths, n, &eo, true);
+        if (!run.alt) return glop_last_error();
+        glop_build_opts cand{};
+        float ms = 0.f;
+        if ((rc = run.time_on(run.alt, cand, &ms)) != GLOP_OK) return rc;
+        if (ms < 0.99f * best) {
+            std::swap(run.h, run.alt);
+            cur = cand;
+            best = ms;
+        }
+    }
+    const uint32_t minlen = run.h->c.min_len;
     glop_build_opts none{};
+    none.prefix_len = cur.prefix_len;
     none.filter = GLOP_FILTER_NONE;
     none.tile_kib = 8;
     if ((rc = consider(none)) != GLOP_OK) return rc;

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <string>
 #include <thread>
 
 #include "glop_layout.hpp"
@@ -26,6 +27,30 @@ uint32_t load_qgram(const uint8_t *p, uint32_t q) {
     uint32_t g = 0;
     for (uint32_t k = 0; k < q; ++k) g |= (uint32_t)p[k] << (8 * k);
     return g;
+}
+
+// Automatic truncation: 8 bytes when some pattern is longer (so truncation
+// shortens walks) and at most 16 patterns share one 8-byte prefix (so each
+// candidate verifies a short list); 0 (whole patterns) otherwise.  Lengths
+// are checked by the caller; invalid input just yields 0 here.
+uint32_t auto_prefix_len(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n) {
+    constexpr uint32_t kLen = 8, kMaxShare = 16;
+    uint32_t longest = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+        if (!patterns[j] || lengths[j] == 0 || lengths[j] > GLOP_MAX_PATTERN_LEN) return 0;
+        longest = std::max(longest, lengths[j]);
+    }
+    if (longest <= kLen) return 0;
+    std::vector<std::string> heads(n);
+    for (uint32_t j = 0; j < n; ++j)
+        heads[j].assign(reinterpret_cast<const char *>(patterns[j]), std::min(kLen, lengths[j]));
+    std::sort(heads.begin(), heads.end());
+    uint32_t run = 1;
+    for (uint32_t j = 1; j < n; ++j) {
+        run = heads[j] == heads[j - 1] ? run + 1 : 1;
+        if (run > kMaxShare) return 0;
+    }
+    return kLen;
 }
 
 }  // namespace
@@ -138,13 +163,15 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
         err = "NULL pattern or length array";
         return GLOP_EINVAL;
     }
-    if (o.prefix_len > 255 || (o.candidates && !o.prefix_len)) {
-        err = "prefix_len must be 0..255, and candidates needs prefix_len";
+    if ((o.prefix_len > 255 && o.prefix_len != GLOP_PREFIX_FULL) ||
+        (o.candidates && (o.prefix_len == 0 || o.prefix_len == GLOP_PREFIX_FULL))) {
+        err = "prefix_len must be 0, 1..255 or GLOP_PREFIX_FULL, and candidates needs an explicit prefix_len";
         return GLOP_EINVAL;
     }
     c = Compiled{};
     c.num_patterns = n;
-    c.prefix_len = o.prefix_len;
+    c.prefix_len = o.prefix_len == GLOP_PREFIX_FULL ? 0u : o.prefix_len;
+    if (o.prefix_len == 0 && n > 0 && patterns && lengths) c.prefix_len = auto_prefix_len(patterns, lengths, n);
     c.candidates = o.candidates ? 1u : 0u;
     c.min_len = n ? 0xFFFFFFFFu : 0;
     bool used[256] = {};

@@ -73,8 +73,12 @@ def test_compiled_trie_matches_oracle_on_workloads(name, n_bytes):
 def test_state_count_is_distinct_prefixes_plus_root():
     pats = synth.gen_patterns(synth.WORKLOADS["medium"].patterns, 5, 77)
     prefixes = {p[:k] for p in pats for k in range(1, len(p) + 1)}
-    info = host_dict(pats).info()
+    info = host_dict(pats, prefix_len=glop.GLOP_PREFIX_FULL).info()
     assert info["num_states"] == len(prefixes) + 1
+    # The automatic engine truncates this dictionary to 8-byte prefixes.
+    heads = {p[:k] for p in pats for k in range(1, min(8, len(p)) + 1)}
+    auto = host_dict(pats).info()
+    assert auto["prefix_len"] == 8 and auto["num_states"] == len(heads) + 1
     assert info["num_classes"] == len({b for p in pats for b in p}) + 1
     assert info["min_len"] == 8 and info["max_len"] <= 64
     # medium dictionary: 4-byte q-grams probed at every aligned word

@@ -79,3 +79,17 @@ def test_prefix_options_are_checked_and_reported():
     assert info["prefix_len"] == 8 and info["candidates"] == 0 and info["max_len"] == 10 and info["min_len"] == 3
     info = host_dict([b"abcdefghij", b"abcdefghkl"], prefix_len=8, candidates=True).info()
     assert info["candidates"] == 1 and info["num_states"] == 9  # root + 8 shared prefix states
+
+
+def test_automatic_engine_rule():
+    # Every pattern fits in 8 bytes: truncation would change nothing.
+    assert host_dict([b"abc", b"abcdefgh"]).info()["prefix_len"] == 0
+    # Longer patterns with distinct heads: 8-byte prefixes plus verification.
+    assert host_dict([b"abcdefghij", b"bcdefghijk"]).info()["prefix_len"] == 8
+    # 16 patterns may share one 8-byte head; 17 may not.
+    share16 = [b"commonhd" + bytes([65 + k]) for k in range(16)]
+    assert host_dict(share16).info()["prefix_len"] == 8
+    assert host_dict(share16 + [b"commonhdZZ"]).info()["prefix_len"] == 0
+    # Explicit choices win.
+    assert host_dict(share16 + [b"commonhdZZ"], prefix_len=8).info()["prefix_len"] == 8
+    assert host_dict([b"abcdefghij"], prefix_len=glop.GLOP_PREFIX_FULL).info()["prefix_len"] == 0
