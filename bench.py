@@ -502,7 +502,7 @@ def main() -> int:
                                 "value_frac": round(value / read_gbs, 4), "scan_frac": round(achieved / read_gbs, 4),
                                 "kernel": "glop_stream_read_kernel (same load shape as the scan)"},
         "dictionary": {k: info[k] for k in ("num_states", "num_classes", "stride", "qgram", "bitmap_log2",
-                                            "filter_keys", "table_bytes")},
+                                            "probe_bits", "filter_keys", "table_bytes", "prefix_len")},
         "paper_context": "20 Gbps (2.5 GB/s) PFAC texture-memory kernel on a Tesla K20m, 100 MB logs, "
                          "patterns truncated to 8 bytes (Sections 7-8); other hardware and problem",
     }
@@ -524,9 +524,9 @@ def main() -> int:
         torch.cuda.synchronize()
         return a_.elapsed_time(b_) / args.steps
 
-    for key, opts, what in (("prefix8", dict(prefix_len=8), "trie of 8-byte prefixes + GPU verify of the rest"),
-                            ("blocked_filter", dict(probe_bits=3), "two filter bits in one word (one LDS read per probe)"),
-                            ("prefix8_blocked", dict(prefix_len=8, probe_bits=3), "both")):
+    for key, opts, what in (("full_trie", dict(prefix_len=glop.GLOP_PREFIX_FULL), "trie of the whole patterns"),
+                            ("prefix8", dict(prefix_len=8), "trie of 8-byte prefixes + GPU verify of the rest"),
+                            ("blocked_filter", dict(probe_bits=3), "two filter bits in one word (one LDS read per probe)")):
         dd = glop.Dict(pats, **opts)
         ms_alt = time_dict(dd)
         result[key] = {"ms_per_step": round(ms_alt, 5), "GBps": round(n / (ms_alt / 1e3) / 1e9, 2),
