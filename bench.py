@@ -366,6 +366,7 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) traces")
     ap.add_argument("--no-host-stream", action="store_true", help="skip the host-streamed input measurement")
+    ap.add_argument("--no-alt", action="store_true", help="skip the alternative engine/filter configurations")
     ap.add_argument("--served-requests", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -398,7 +399,11 @@ def main() -> int:
     ws = ws_buf[(-ws_buf.data_ptr()) % 256:][:ws_bytes]
     stream = torch.cuda.current_stream()
     hev = HipEvents()
-    evs = [[hev.create() for _ in range(3)] for _ in range(args.steps)]
+    # Kernel-duration events ride on every 8th timed call only: an event
+    # record between launches costs a few microseconds of its own.
+    sampled = list(range(0, args.steps, 8))
+    scan_evs = {k: (hev.create(), hev.create()) for k in sampled}
+    step_evs = [(hev.create(), hev.create()) for _ in range(args.steps)]
 
     for _ in range(args.warmup):
         d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
@@ -412,15 +417,21 @@ def main() -> int:
     torch.cuda.synchronize()
     start.record(stream)
     for k in range(args.steps):
-        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream, events=evs[k])
+        ev = (scan_evs[k][0], scan_evs[k][1], None) if k in scan_evs else None
+        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream, events=ev)
     end.record(stream)
     torch.cuda.synchronize()
     wall_ms = start.elapsed_time(end)
     ms_per_step = wall_ms / args.steps
-    scan_ms = np.array([hev.elapsed_ms(e[0], e[1]) for e in evs])
-    step_ms = np.array([hev.elapsed_ms(e[0], e[2]) for e in evs])
-    for e in evs:
-        for x in e:
+    scan_ms = np.array([hev.elapsed_ms(a_, b_) for a_, b_ in scan_evs.values()])
+    # Per-call latency distribution (first kernel start to last kernel end), its own loop.
+    for k in range(args.steps):
+        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream,
+                     events=(step_evs[k][0], None, step_evs[k][1]))
+    torch.cuda.synchronize()
+    step_ms = np.array([hev.elapsed_ms(a_, b_) for a_, b_ in step_evs])
+    for pair in list(scan_evs.values()) + step_evs:
+        for x in pair:
             hev.destroy(x)
 
     # Correctness of the timed result (outside the timed region).
@@ -497,6 +508,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.workload),
                      "kernel": "glop_scan_kernel", "kernel_ms_avg": round(scan_avg, 5),
+                     "kernel_event_samples": int(scan_ms.size),
                      "algorithmic_bytes_per_launch": int(scan_bytes)},
         "read_stream_ceiling": {"GBps": round(read_gbs, 1), "ms": round(read_ms, 5),
                                 "value_frac": round(value / read_gbs, 4), "scan_frac": round(achieved / read_gbs, 4),
@@ -524,9 +536,11 @@ def main() -> int:
         torch.cuda.synchronize()
         return a_.elapsed_time(b_) / args.steps
 
-    for key, opts, what in (("full_trie", dict(prefix_len=glop.GLOP_PREFIX_FULL), "trie of the whole patterns"),
-                            ("prefix8", dict(prefix_len=8), "trie of 8-byte prefixes + GPU verify of the rest"),
-                            ("blocked_filter", dict(probe_bits=3), "two filter bits in one word (one LDS read per probe)")):
+    alt = () if args.no_alt else (
+        ("full_trie", dict(prefix_len=glop.GLOP_PREFIX_FULL), "trie of the whole patterns"),
+        ("prefix8", dict(prefix_len=8), "trie of 8-byte prefixes + GPU verify of the rest"),
+        ("blocked_filter", dict(probe_bits=3), "two filter bits in one word (one LDS read per probe)"))
+    for key, opts, what in alt:
         dd = glop.Dict(pats, **opts)
         ms_alt = time_dict(dd)
         result[key] = {"ms_per_step": round(ms_alt, 5), "GBps": round(n / (ms_alt / 1e3) / 1e9, 2),

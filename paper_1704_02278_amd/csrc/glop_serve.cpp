@@ -340,6 +340,16 @@ struct glop_server {
                 // request needs).
                 done.clear();
                 while (!held.empty()) release_held_locked(held.begin()->first);
+                if (error != GLOP_OK) {
+                    // After a failed launch or allocation nothing waiting can
+                    // be trusted to run: drop it.
+                    for (auto &q : pending) {
+                        outstanding -= q.size();
+                        q.clear();
+                    }
+                    outstanding -= fifo.size();
+                    fifo.clear();
+                }
             }
             for (;;) {
                 const bool launched = o.mode == GLOP_SERVE_PLAIN ? launch_plain_locked() : launch_batched_locked();

@@ -40,7 +40,7 @@ def kernel_sources_sha256(root: Path = ROOT) -> str:
 
 def short_name(name: str) -> str:
     """Kernel name without namespaces, return type and parameter list."""
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
     for prefix in ("void ", "glop::detail::", "glop::"):
         n = n.replace(prefix, "")
     return n.strip()
