@@ -370,8 +370,8 @@ def main() -> int:
     ap.add_argument("--served-requests", type=int, default=20000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the matcher has no multi-GPU path "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the matcher has no multi-GPU path",
+              file=sys.stderr)
         return 2
 
     import torch
@@ -547,6 +547,28 @@ def main() -> int:
                        "vs_default": round(ms_per_step / ms_alt, 3), "num_states": dd.info()["num_states"],
                        "config": what}
         del dd
+
+    if not args.no_alt:
+        # The autotuner on an independent sample of the same recipe (another
+        # seed), then the chosen options on the benchmark text.
+        import dataclasses
+
+        w = synth.WORKLOADS[args.workload]
+        spec = dataclasses.replace(w.text, n_bytes=min(n, 256 << 20))
+        sample_text = synth.gen_text(spec, synth.BASE_SEED + 1, synth.STREAM_TEXT + w.index)
+        synth.plant(sample_text, pats, spec.plant_every, synth.BASE_SEED + 1, synth.STREAM_PLANTS + w.index)
+        sample = torch.from_numpy(sample_text).to(dev)
+        t0 = time.perf_counter()
+        tuned = glop.autotune(pats, sample)
+        tune_s = time.perf_counter() - t0
+        del sample
+        dt_ = glop.Dict(pats, **tuned["opts"])
+        ms_tuned = time_dict(dt_)
+        del dt_
+        result["autotune"] = {"opts": tuned["opts"], "evaluated": tuned["evaluated"], "seconds": round(tune_s, 2),
+                              "sample_ms_auto": round(tuned["auto_ms"], 5), "sample_ms_tuned": round(tuned["ms"], 5),
+                              "ms_per_step": round(ms_tuned, 5), "GBps": round(n / (ms_tuned / 1e3) / 1e9, 2),
+                              "sample": "256 MiB of the same text recipe and dictionary, another seed"}
 
     if not args.no_host_stream:
         log("[bench] host-streamed input ...")

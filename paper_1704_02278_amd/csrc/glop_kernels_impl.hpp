@@ -132,7 +132,7 @@ struct ScanParams {
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
     uint64_t *tile_rec;          // records per tile
     uint32_t *tile_nm;           // matched starts per tile
-    uint64_t *staging;           // kStageCap per tile: (offset in tile << 32) | state
+    uint64_t *staging;           // kStageCap per tile: stage_entry() words
     uint64_t *itemsum;           // records per work item
     uint64_t *counts;            // per-pattern counts
     uint32_t zero_counts;        // single text: the scan kernel clears the counts first
@@ -382,14 +382,30 @@ __device__ __forceinline__ bool verified(const GlopDevDict &d, const Span &s, ui
     return true;
 }
 
-// Records at coordinate x of a walk whose deepest terminal is st.
-__device__ __forceinline__ uint32_t state_records(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t st) {
+// Records at coordinate x of a walk whose deepest terminal is st.  With a
+// verify stage, `pass` receives which of the first 16 listed patterns passed
+// (bit k for the k-th), valid when the list has at most 16 entries.
+__device__ __forceinline__ uint32_t state_records(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t st,
+                                                  uint32_t &pass) {
     const uint32_t cnt = d.term[2 * st + 1];
+    pass = 0;
     if (!d.verify_from) return cnt;
     const uint32_t first = d.term[2 * st];
     uint32_t n = 0;
-    for (uint32_t k = 0; k < cnt; ++k) n += verified(d, s, x, d.outids[first + k]) ? 1u : 0u;
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const bool ok = verified(d, s, x, d.outids[first + k]);
+        n += ok ? 1u : 0u;
+        if (ok && k < 16) pass |= 1u << k;
+    }
     return n;
+}
+
+// A staged matched start, ordered by its offset in the tile (top 15 bits):
+// offset << 49 | pass-mask-valid << 48 | pass mask << 32 | deepest terminal.
+// The mask (state_records) spares the emit kernel a second verification.
+__device__ __forceinline__ uint64_t stage_entry(const GlopDevDict &d, uint32_t off, uint32_t st, uint32_t pass) {
+    const uint64_t valid = (d.verify_from && d.term[2 * st + 1] <= 16) ? 1ull : 0ull;
+    return ((uint64_t)off << 49) | (valid << 48) | ((uint64_t)(pass & 0xFFFFu) << 32) | st;
 }
 
 // Where tile t lies: its text (or chunk), its first coordinate, and whether
@@ -456,12 +472,13 @@ struct StageSink {
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
-        const uint32_t cnt = last ? state_records(P.d, ti.s, ti.x0 + off, last) : 0u;
+        uint32_t pass = 0;
+        const uint32_t cnt = last ? state_records(P.d, ti.s, ti.x0 + off, last, pass) : 0u;
         const bool m = cnt != 0;
         const uint64_t bal = __ballot(m);
         if (bal == 0) return;
         const uint32_t pos = nm + (uint32_t)__popcll(bal & lanemask_lt());
-        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = ((uint64_t)off << 32) | last;
+        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = stage_entry(P.d, off, last, pass);
         nm += (uint32_t)__popcll(bal);
         rec += wave_sum_u32(cnt);
     }
@@ -484,7 +501,8 @@ struct DirectSink {
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
         const uint64_t x = ti.x0 + off;
-        const uint32_t cnt = last ? state_records(P.d, ti.s, x, last) : 0u;
+        uint32_t pass = 0;
+        const uint32_t cnt = last ? state_records(P.d, ti.s, x, last, pass) : 0u;
         const bool m = cnt != 0;
         if (__ballot(m) == 0) return;
         uint32_t tot;
@@ -671,18 +689,18 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
     const uint32_t t_rel = ent >> kPosBits;
     const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
     const uint64_t t = tb + t_rel;
-    uint32_t last = 0, nrec = 0;
+    uint32_t last = 0, nrec = 0, pass = 0;
     if (act) {
         const TileInfo ti = tile_info<BATCH, TILE>(P, t);
         const uint64_t x = ti.x0 + (int64_t)off;
         if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) {
             last = walk(P.d, ti.s, cls, x);
-            if (last) nrec = state_records(P.d, ti.s, x, last);
+            if (last) nrec = state_records(P.d, ti.s, x, last, pass);
         }
     }
     if (nrec) {
         const uint32_t slot = atomicAdd(&nm_l[t_rel], 1u);
-        if (slot < kStageCap) P.staging[t * kStageCap + slot] = ((uint64_t)off << 32) | last;
+        if (slot < kStageCap) P.staging[t * kStageCap + slot] = stage_entry(P.d, (uint32_t)off, last, pass);
         atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)nrec);
     }
 }
@@ -1006,12 +1024,16 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                         }
                         prev = ent;
                         const uint32_t st = (uint32_t)ent;
-                        const uint64_t x = ti.x0 + (ent >> 32);
+                        const uint64_t x = ti.x0 + (ent >> 49);
+                        const bool have_mask = (ent >> 48) & 1u;
+                        const uint32_t pass = (uint32_t)(ent >> 32) & 0xFFFFu;
                         const uint64_t i = x - ti.s.head + E.offset_add;
                         const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
                         for (uint32_t k = 0; k < cnt; ++k) {
                             const uint32_t id = P.d.outids[first + k];
-                            if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
+                            if (P.d.verify_from &&
+                                !(have_mask ? ((pass >> k) & 1u) != 0 : verified(P.d, ti.s, x, id)))
+                                continue;
                             if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
                             atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
                             ++pos;
