@@ -83,13 +83,14 @@ typedef struct glop_dict *glop_handle_t;
  *               the shortest pattern length.
  *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
  *               resident in LDS).
- *   probe_bits  0 = automatic (2); 1 or 2 bits per q-gram at independent
+ *   probe_bits  0 = automatic (3 at stride 1, where the probes' LDS reads
+ *               dominate; 2 at stride 4, where the walks of false positives
+ *               do); 1 or 2 bits per q-gram at independent
  *               positions (a Bloom filter with one or two hash functions), or
  *               3 = two bits within one 32-bit word chosen by one hash (a
- *               blocked Bloom filter: one lookup per probe; 8 KiB tiles only).
- *   tile_kib    0 = automatic (8); 8 or 16: bytes of text one wavefront streams
- *               per tile (16 bytes per lane per round, 8 or 16 rounds).  16 is
- *               available with the stride-4 filter only.
+ *               blocked Bloom filter: one lookup per probe).
+ *   tile_kib    0 = automatic, or 8: KiB of text one wavefront streams per
+ *               tile (16 bytes per lane per round, 8 rounds).
  *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;
  *               1..255 = the trie holds each pattern's first prefix_len bytes
  *               only (the library of Sections 2 and 5 truncates patterns to 8
@@ -260,7 +261,7 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
 
 /*
  * Match every chunk of a batch in one persistent scan launch that takes work
- * items (runs of 8 or 16 KiB tiles, any mix of chunks) from a device work
+ * items (runs of 8 KiB tiles, any mix of chunks) from a device work
  * queue, then one ordered emit launch.  Everything is enqueued on `stream`
  * and reads its inputs from device memory only, so a captured hipGraph can be
  * replayed after the chunk table (and the chunks) change, as long as nchunks
@@ -446,7 +447,7 @@ int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, co
  * (prefilter, then full comparison) has free parameters the paper fixes for
  * its own hardware; here they are measured.  Starting from the automatic
  * options, one parameter at a time is varied (filter on or off, q-gram
- * length, stride, probe bits, bitmap size, tile size) and a change is kept
+ * length, stride, probe bits, bitmap size) and a change is kept
  * when it is at least 1 % faster (median of 7 timed calls after 2 warm-up
  * calls).  Every option set is exact, so all of them must report the same
  * number of matches on the sample; a difference fails the call.  The trie is

@@ -474,7 +474,6 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             if (pb == pb0) continue;
             glop_build_opts cand = cur;
             cand.probe_bits = pb;
-            if (pb == 3) cand.tile_kib = 8;
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
         const uint32_t lg0 = cur.bitmap_log2;
@@ -482,11 +481,6 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             if (lg == lg0) continue;
             glop_build_opts cand = cur;
             cand.bitmap_log2 = lg;
-            if ((rc = consider(cand)) != GLOP_OK) return rc;
-        }
-        if (cur.stride == 4) {
-            glop_build_opts cand = cur;
-            cand.tile_kib = cur.tile_kib == 16 ? 8u : 16u;
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
     }

@@ -14,10 +14,6 @@ GLOP_DECLARE_VARIANT(4, 1, 1, 0, 8)
 GLOP_DECLARE_VARIANT(4, 1, 1, 1, 8)
 GLOP_DECLARE_VARIANT(4, 1, 2, 0, 8)
 GLOP_DECLARE_VARIANT(4, 1, 2, 1, 8)
-GLOP_DECLARE_VARIANT(4, 1, 1, 0, 16)
-GLOP_DECLARE_VARIANT(4, 1, 1, 1, 16)
-GLOP_DECLARE_VARIANT(4, 1, 2, 0, 16)
-GLOP_DECLARE_VARIANT(4, 1, 2, 1, 16)
 GLOP_DECLARE_VARIANT(1, 1, 3, 0, 8)
 GLOP_DECLARE_VARIANT(1, 1, 3, 1, 8)
 GLOP_DECLARE_VARIANT(4, 1, 3, 0, 8)
@@ -34,10 +30,6 @@ const VariantFns &variant_for(const GlopDevDict &d) {
         return q4 ? GLOP_VARIANT_ID(1, 1, 3, 1, 8)() : GLOP_VARIANT_ID(1, 1, 3, 0, 8)();
     }
     if (d.stride == 4) {
-        if (d.tile_kib == 16) {
-            if (k2) return q4 ? GLOP_VARIANT_ID(4, 1, 2, 1, 16)() : GLOP_VARIANT_ID(4, 1, 2, 0, 16)();
-            return q4 ? GLOP_VARIANT_ID(4, 1, 1, 1, 16)() : GLOP_VARIANT_ID(4, 1, 1, 0, 16)();
-        }
         if (k2) return q4 ? GLOP_VARIANT_ID(4, 1, 2, 1, 8)() : GLOP_VARIANT_ID(4, 1, 2, 0, 8)();
         return q4 ? GLOP_VARIANT_ID(4, 1, 1, 1, 8)() : GLOP_VARIANT_ID(4, 1, 1, 0, 8)();
     }
@@ -91,9 +83,7 @@ hipError_t prepare_kernels() {
                                &GLOP_VARIANT_ID(1, 1, 1, 1, 8)(),  &GLOP_VARIANT_ID(1, 1, 2, 0, 8)(),
                                &GLOP_VARIANT_ID(1, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 1, 0, 8)(),
                                &GLOP_VARIANT_ID(4, 1, 1, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 2, 0, 8)(),
-                               &GLOP_VARIANT_ID(4, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 1, 0, 16)(),
-                               &GLOP_VARIANT_ID(4, 1, 1, 1, 16)(), &GLOP_VARIANT_ID(4, 1, 2, 0, 16)(),
-                               &GLOP_VARIANT_ID(4, 1, 2, 1, 16)(),  &GLOP_VARIANT_ID(1, 1, 3, 0, 8)(),
+                               &GLOP_VARIANT_ID(4, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(1, 1, 3, 0, 8)(),
                                &GLOP_VARIANT_ID(1, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(4, 1, 3, 0, 8)(),
                                &GLOP_VARIANT_ID(4, 1, 3, 1, 8)()};
     for (const VariantFns *v : all) {

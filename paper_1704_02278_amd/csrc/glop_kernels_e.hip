@@ -1,12 +1,11 @@
-// Instantiations of the matching kernels (one group per translation unit,
-// so the groups compile in parallel).
+// Kernel variants: blocked two-bit filter (probe_bits 3), both strides, 8 KiB tiles.
 #include "glop_kernels_impl.hpp"
 
 namespace glop {
 namespace detail {
-
-GLOP_DEFINE_VARIANT(4, 1, 1, 0, 16)
-GLOP_DEFINE_VARIANT(4, 1, 1, 1, 16)
-
+GLOP_DEFINE_VARIANT(1, 1, 3, 0, 8)
+GLOP_DEFINE_VARIANT(1, 1, 3, 1, 8)
+GLOP_DEFINE_VARIANT(4, 1, 3, 0, 8)
+GLOP_DEFINE_VARIANT(4, 1, 3, 1, 8)
 }  // namespace detail
 }  // namespace glop

@@ -95,13 +95,13 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
                 err = "bitmap_log2 must be 12..19";
                 return GLOP_EINVAL;
             }
-            uint32_t k = o.probe_bits ? o.probe_bits : 2u;
+            // Automatic probe: at stride 1 every offset is probed and the LDS
+            // reads dominate, so one read per probe (blocked, 3) wins despite
+            // its higher false-positive rate; at stride 4 walks dominate and
+            // two independent bits (2) win.
+            uint32_t k = o.probe_bits ? o.probe_bits : (stride == 1 ? 3u : 2u);
             if (k != 1 && k != 2 && k != 3) {
                 err = "probe_bits must be 1, 2 or 3";
-                return GLOP_EINVAL;
-            }
-            if (k == 3 && o.tile_kib == 16) {
-                err = "16 KiB tiles are built for probe_bits 1 and 2";
                 return GLOP_EINVAL;
             }
             c.qgram = q;
@@ -136,12 +136,8 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             c.bitmap.assign((1u << 12) / 32, 0);
         }
         c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
-        if (c.tile_kib != 8 && c.tile_kib != 16) {
-            err = "tile_kib must be 8 or 16";
-            return GLOP_EINVAL;
-        }
-        if (c.tile_kib == 16 && !(c.filter == GLOP_FILTER_QGRAM && c.stride == 4)) {
-            err = "16 KiB tiles need the stride-4 filter";
+        if (c.tile_kib != 8) {
+            err = "tile_kib must be 0 (automatic) or 8";
             return GLOP_EINVAL;
         }
     } catch (const std::bad_alloc &) {

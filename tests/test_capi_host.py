@@ -158,3 +158,9 @@ def test_server_create_argument_checks():
     glop.glop_server_destroy(None)  # ignored
     t0 = glop.glop_now_ns()
     assert glop.glop_now_ns() >= t0 > 0
+
+
+def test_removed_tile_size_is_rejected():
+    with pytest.raises(glop.GlopError):
+        host_dict([b"abcdefgh"], tile_kib=16)
+    assert host_dict([b"abcdefgh"], tile_kib=8).info()["tile_kib"] == 8

@@ -67,10 +67,7 @@ def test_batch_equals_each_chunk_alone(name):
     pats, text, _ = synth.make_workload(name, n_bytes=24 << 20)
     pieces = _mixed_pieces(text, rng, 150)
     buf, chunks = _chunks_in_one_buffer(pieces)
-    variants = variants_for(pats)
-    if min(len(p) for p in pats) >= 7:
-        variants.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, tile_kib=16))
-        variants.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, tile_kib=16, probe_bits=1))
+    variants = variants_for(pats) + [dict(prefix_len=glop.GLOP_PREFIX_FULL)]
     for opts in variants:
         say("batch", name, len(pieces), opts)
         d = glop.Dict(pats, **opts)
@@ -117,7 +114,7 @@ def test_batch_dense_chunks_take_the_rescan_path():
     pats = [b"abcdefg", b"cdefgab", b"bcdefga"]
     pieces = [(b"abcdefg" * 9000)[: 60_000 + 17 * k] for k in range(12)] + [b"", b"abc", b"xyz" * 1000]
     buf, chunks = _chunks_in_one_buffer(pieces, shift=5)
-    for opts in (dict(), dict(tile_kib=16), dict(filter=glop.GLOP_FILTER_QGRAM, stride=1)):
+    for opts in (dict(), dict(prefix_len=glop.GLOP_PREFIX_FULL), dict(filter=glop.GLOP_FILTER_QGRAM, stride=1)):
         say("batch-dense", opts)
         d = glop.Dict(pats, **opts)
         _check_batch(d, pats, pieces, chunks, d.match_batch(chunks))
