@@ -483,7 +483,9 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
 /* ---- Measurement helper -----------------------------------------------------
  *
  * glop_stream_read: read the first floor(len / 16) * 16 bytes at d_data once,
- * with the same 16-byte-per-lane coalesced loads as the scan kernel, and fold
+ * with the scan kernel's load shape (the same split into per-workgroup items
+ * of 8 KiB tiles, 16-byte coalesced non-temporal loads per lane, one tile of
+ * loads in flight ahead of use) and nothing else, and fold
  * them into the device uint64_t at d_sink (its value afterwards depends on
  * every byte read and is otherwise unspecified).  Its rate is
  * the practical ceiling for a pure HBM read stream on this device, against

@@ -37,22 +37,38 @@ const VariantFns &variant_for(const GlopDevDict &d) {
     return q4 ? GLOP_VARIANT_ID(1, 1, 1, 1, 8)() : GLOP_VARIANT_ID(1, 1, 1, 0, 8)();
 }
 
-// Read stream with the scan kernel's load shape: each wave takes 8 KiB tiles,
-// a lane loads 16 bytes per 1 KiB round, all eight rounds in flight at once.
-__global__ __launch_bounds__(kBlock) void glop_stream_read_kernel(const uint4 *p, uint64_t n16, uint64_t *sink) {
-    constexpr uint32_t kTile16 = 8 * kWave;  // 16-byte units per 8 KiB tile
-    const uint64_t waves = (uint64_t)gridDim.x * kWaves;
-    uint32_t acc = 0;
-    for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave_id(); tile * kTile16 < n16; tile += waves) {
-        const uint64_t base = tile * kTile16 + lane_id();
-        uint4 v[8];
+// Read stream with the scan kernel's load shape and nothing else: workgroup b
+// takes the 8 KiB tiles [b * tpi, (b + 1) * tpi), wave w every 16th of them
+// from the w-th, a lane 16 bytes of each 1 KiB round with non-temporal loads,
+// and a tile's loads go out as soon as the one before it is consumed.
+__global__ __launch_bounds__(kBlock) void glop_stream_read_kernel(const uint8_t *p, uint64_t n16, uint64_t tpi,
+                                                                 uint64_t *sink) {
+    constexpr uint64_t kTile16 = 8 * kWave;  // 16-byte units per 8 KiB tile
+    const uint64_t ntiles = (n16 + kTile16 - 1) / kTile16;
+    const uint64_t tb = (uint64_t)blockIdx.x * tpi;
+    const uint64_t te = min(ntiles, tb + tpi);
+    const uint64_t lane = lane_id();
+    uint4 v[8];
+    auto load = [&](uint64_t t) {
+        const uint64_t base = t * kTile16 + lane;
+        if ((t + 1) * kTile16 <= n16) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint64_t i = base + (uint64_t)k * kWave;
-            v[k] = i < n16 ? p[i] : make_uint4(0u, 0u, 0u, 0u);
+            for (int k = 0; k < 8; ++k) v[k] = load_stream16(p + (base + (uint64_t)k * kWave) * 16);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint64_t i = base + (uint64_t)k * kWave;
+                v[k] = i < n16 ? *reinterpret_cast<const uint4 *>(p + i * 16) : make_uint4(0u, 0u, 0u, 0u);
+            }
         }
+    };
+    uint32_t acc = 0;
+    uint64_t t = tb + wave_id();
+    if (t < te) load(t);
+    for (; t < te; t += kWaves) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc ^= v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+        if (t + kWaves < te) load(t + kWaves);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o);
@@ -150,9 +166,14 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
 }
 
 hipError_t launch_stream_read(const uint8_t *data, uint64_t len, uint64_t *sink, int num_cus, hipStream_t stream) {
-    const uint32_t grid = 2u * (uint32_t)(num_cus > 0 ? num_cus : 1);  // two 1024-thread groups per CU
-    hipLaunchKernelGGL(glop_stream_read_kernel, dim3(grid), dim3(kBlock), 0, stream,
-                       reinterpret_cast<const uint4 *>(data), len / 16, sink);
+    // The single-text scan's item split: one item per CU, at most 512 tiles each.
+    const uint64_t n16 = len / 16, ntiles = (n16 + 8 * kWave - 1) / (8 * kWave);
+    if (ntiles == 0) return hipSuccess;
+    const uint64_t cus = (uint64_t)(num_cus > 0 ? num_cus : 1);
+    uint64_t tpi = (ntiles + cus - 1) / cus;
+    if (tpi > kMaxTilesPerItem) tpi = kMaxTilesPerItem;
+    const uint32_t grid = (uint32_t)((ntiles + tpi - 1) / tpi);
+    hipLaunchKernelGGL(glop_stream_read_kernel, dim3(grid), dim3(kBlock), 0, stream, data, n16, tpi, sink);
     return hipGetLastError();
 }
 

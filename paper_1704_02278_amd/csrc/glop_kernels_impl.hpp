@@ -247,6 +247,19 @@ __device__ __forceinline__ uint32_t keep_bytes(uint32_t w, int64_t x, int64_t lo
     return w & hi_mask & ~lo_mask;
 }
 
+// 16 bytes at an aligned address; NT marks the load non-temporal (the text is
+// streamed once, so its lines are the first the caches may give up).
+template <bool NT = true>
+__device__ __forceinline__ uint4 load_stream16(const uint8_t *p) {
+    if constexpr (NT) {
+        typedef unsigned v4u __attribute__((ext_vector_type(4)));
+        const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const uint4 *>(p);
+    }
+}
+
 // 16 text bytes at aligned coordinate x; bytes outside the text read as 0.
 // An aligned 16-byte block holding at least one text byte lies in the same
 // page as that byte, so it is read whole and the outside bytes are masked;
@@ -443,13 +456,16 @@ struct TileRegs {
     uint32_t extra;
 };
 
-template <int R, bool FILTER>
+// A tile's bytes into registers.  NT: non-temporal loads, for the stride-4
+// filter, whose walks rarely re-read the text; the stride-1 walks re-read
+// their windows right after the load and want them kept in L2.
+template <int R, bool FILTER, bool NT = false>
 __device__ __forceinline__ void load_tile(const TileInfo &ti, TileRegs<R> &r) {
     const uint64_t x = ti.x0 + lane_id() * 16u;
     if (ti.interior) {
         const uint8_t *p = ti.s.abase + x;
 #pragma unroll
-        for (int k = 0; k < R; ++k) r.v[k] = *reinterpret_cast<const uint4 *>(p + k * kRoundBytes);
+        for (int k = 0; k < R; ++k) r.v[k] = load_stream16<NT>(p + k * kRoundBytes);
         r.extra = FILTER ? *reinterpret_cast<const uint32_t *>(ti.s.abase + ti.x0 + R * kRoundBytes) : 0u;
     } else {
 #pragma unroll
@@ -843,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
     constexpr bool kDefer = STRIDE == 4;
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t hl_count, item_failed;
+    __shared__ uint32_t hl_count, item_failed, tile_next;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
@@ -874,9 +890,19 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull)
                         : (uint64_t)blockIdx.x;
         item_failed = 0;
+        tile_next = 0;
         if (kDefer) hl_count = 0;
     }
     reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
+    // A wave takes the item's next tile from an LDS counter whenever it starts
+    // one, so all 16 waves keep loads in flight until the item's last tile (a
+    // fixed share per wave left some waves idle for a fifth of the item while
+    // others were still streaming).
+    auto claim = [&]() -> uint32_t {
+        uint32_t c = 0;
+        if (lane_id() == 0) c = atomicAdd(&tile_next, 1u);
+        return __builtin_amdgcn_readfirstlane(c);
+    };
     for (;;) {
         __syncthreads();
         const uint64_t item = item_sh;
@@ -886,23 +912,26 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
 
         // Pipelined: once a tile's filter bits are known its bytes are dead,
         // so the next tile's loads go out before anything else.
+        const uint32_t ntile = (uint32_t)(te - tb);
         TileRegs<R> r;
         TileInfo cur{};
-        uint64_t t = tb + wave;
-        if (t < te) {
-            cur = tile_info<BATCH, TILE>(P, t);
-            load_tile<R, FILTER>(cur, r);
+        uint32_t c = claim();
+        if (c < ntile) {
+            cur = tile_info<BATCH, TILE>(P, tb + c);
+            load_tile<R, FILTER, kDefer>(cur, r);
         }
-        for (; t < te; t += kWaves) {
-            const bool has_next = t + kWaves < te;
+        while (c < ntile) {
+            const uint64_t t = tb + c;
+            const uint32_t cn = claim();
+            const bool has_next = cn < ntile;
             TileInfo nxt = cur;
-            if (has_next) nxt = tile_info<BATCH, TILE>(P, t + kWaves);
+            if (has_next) nxt = tile_info<BATCH, TILE>(P, tb + cn);
             StageSink sink(nm_l, rec_l, tb);
             if constexpr (STRIDE == 4) {
                 HitBits<R> pbits;
                 uint32_t xb;
                 tile_hits4<R, K, Q4>(P.d, r, bm, pbits, xb);
-                if (has_next) load_tile<R, FILTER>(nxt, r);
+                if (has_next) load_tile<R, FILTER, true>(nxt, r);
                 if (__ballot(pbits != 0) != 0 || xb) {
                     if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
                         walk_hits4<R>(P, t, cur, pbits, xb, cls, queue, sink);
@@ -914,6 +943,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 walk_offsets1<R>(P, t, cur, m, cls, queue, sink);
             }
             cur = nxt;
+            c = cn;
         }
         if (kDefer) {
             // The rest of the list, shared by all waves.
@@ -936,6 +966,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             P.itemsum[item] = item_failed ? kItemFailed : part;
             item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull) : ~0ull;
             item_failed = 0;
+            tile_next = 0;
             if (kDefer) hl_count = 0;
         }
         reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
