@@ -399,11 +399,12 @@ def main() -> int:
     ws = ws_buf[(-ws_buf.data_ptr()) % 256:][:ws_bytes]
     stream = torch.cuda.current_stream()
     hev = HipEvents()
-    # Kernel-duration events ride on every 8th timed call only: an event
-    # record between launches costs a few microseconds of its own.
-    sampled = list(range(0, args.steps, 8))
-    scan_evs = {k: (hev.create(), hev.create()) for k in sampled}
-    step_evs = [(hev.create(), hev.create()) for _ in range(args.steps)]
+    # The throughput loop carries no events (a timed event record between two
+    # launches costs several microseconds of GPU time).  A second loop of the
+    # same K calls records, around every call, the start and end of the scan
+    # kernel and the end of the emit kernel: the scan kernel's duration for the
+    # roofline and the per-call latency.
+    call_evs = [(hev.create(), hev.create(), hev.create()) for _ in range(args.steps)]
 
     for _ in range(args.warmup):
         d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
@@ -417,21 +418,19 @@ def main() -> int:
     torch.cuda.synchronize()
     start.record(stream)
     for k in range(args.steps):
-        ev = (scan_evs[k][0], scan_evs[k][1], None) if k in scan_evs else None
-        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream, events=ev)
+        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream)
     end.record(stream)
     torch.cuda.synchronize()
     wall_ms = start.elapsed_time(end)
     ms_per_step = wall_ms / args.steps
-    scan_ms = np.array([hev.elapsed_ms(a_, b_) for a_, b_ in scan_evs.values()])
-    # Per-call latency distribution (first kernel start to last kernel end), its own loop.
+    # Kernel durations and per-call latency (scan start to emit end), own loop.
     for k in range(args.steps):
-        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream,
-                     events=(step_evs[k][0], None, step_evs[k][1]))
+        d.match_into(t_dev, out, counts, total=total, workspace=ws, stream=stream, events=call_evs[k])
     torch.cuda.synchronize()
-    step_ms = np.array([hev.elapsed_ms(a_, b_) for a_, b_ in step_evs])
-    for pair in list(scan_evs.values()) + step_evs:
-        for x in pair:
+    scan_ms = np.array([hev.elapsed_ms(a_, b_) for a_, b_, _ in call_evs])
+    step_ms = np.array([hev.elapsed_ms(a_, c_) for a_, _, c_ in call_evs])
+    for trio in call_evs:
+        for x in trio:
             hev.destroy(x)
 
     # Correctness of the timed result (outside the timed region).
@@ -549,12 +548,12 @@ def main() -> int:
         del dd
 
     if not args.no_alt:
-        # The autotuner on an independent sample of the same recipe (another
-        # seed), then the chosen options on the benchmark text.
+        # The autotuner on an independent sample of the same recipe and size
+        # (another seed), then the chosen options on the benchmark text.
         import dataclasses
 
         w = synth.WORKLOADS[args.workload]
-        spec = dataclasses.replace(w.text, n_bytes=min(n, 256 << 20))
+        spec = dataclasses.replace(w.text, n_bytes=n)
         sample_text = synth.gen_text(spec, synth.BASE_SEED + 1, synth.STREAM_TEXT + w.index)
         synth.plant(sample_text, pats, spec.plant_every, synth.BASE_SEED + 1, synth.STREAM_PLANTS + w.index)
         sample = torch.from_numpy(sample_text).to(dev)
@@ -568,7 +567,7 @@ def main() -> int:
         result["autotune"] = {"opts": tuned["opts"], "evaluated": tuned["evaluated"], "seconds": round(tune_s, 2),
                               "sample_ms_auto": round(tuned["auto_ms"], 5), "sample_ms_tuned": round(tuned["ms"], 5),
                               "ms_per_step": round(ms_tuned, 5), "GBps": round(n / (ms_tuned / 1e3) / 1e9, 2),
-                              "sample": "256 MiB of the same text recipe and dictionary, another seed"}
+                              "sample": "a text of the same recipe, size and dictionary, another seed"}
 
     if not args.no_host_stream:
         log("[bench] host-streamed input ...")

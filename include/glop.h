@@ -320,6 +320,9 @@ typedef struct {
     uint32_t candidates;     /* 1 if unverified prefix candidates are reported */
     uint64_t device_bytes;   /* device memory held by the handle */
     int32_t device;          /* HIP device id, or -1 for a host-only handle */
+    uint32_t prefix_keys;    /* distinct 4-byte pattern prefixes in the prefix table
+                                (0: no table, some pattern is shorter than 4 bytes) */
+    uint32_t prefix_slots;   /* slots of the prefix table (a power of two, or 0) */
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 
@@ -446,10 +449,13 @@ int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, co
  * device sample of representative text.  The filter of Sections 2 and 5
  * (prefilter, then full comparison) has free parameters the paper fixes for
  * its own hardware; here they are measured.  Starting from the automatic
- * options, one parameter at a time is varied (filter on or off, q-gram
- * length, stride, probe bits, bitmap size) and a change is kept
- * when it is at least 1 % faster (median of 7 timed calls after 2 warm-up
- * calls).  Every option set is exact, so all of them must report the same
+ * options, the engine (whole patterns or 8-byte prefixes) and then one
+ * parameter at a time is varied (filter on or off, q-gram length, stride,
+ * probe bits, bitmap size) and a change is kept when it is at least 3 %
+ * faster (median of 11 timed calls after 2 warm-up calls).  The sample should
+ * be as large as the texts to be matched: per-call costs that do not scale
+ * with the text (table staging, the end of each work item) weigh more on a
+ * small one.  Every option set is exact, so all of them must report the same
  * number of matches on the sample; a difference fails the call.  The trie is
  * built and uploaded once; candidates differ only in their filter tables.
  *

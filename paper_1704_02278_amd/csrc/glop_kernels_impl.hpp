@@ -86,17 +86,27 @@ constexpr uint64_t kItemFailed = ~0ull;
 template <int STRIDE>
 constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
 
+// Largest prefix table the scan kernel stages in LDS (what the rest of its
+// layout leaves of the 160 KiB).  A larger one is not used: a hashed lookup in
+// global memory costs about what the first steps through the transition
+// table's hot root rows cost (measured slower on a 20,000-pattern dictionary).
+template <int STRIDE>
+constexpr uint32_t r4_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
+
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
-// per-tile matched-start counts | per-tile record counts.
+// per-tile matched-start counts | per-tile record counts | prefix table (scan
+// kernel, when staged).
 template <int STRIDE>
 struct LdsLayout {
     uint32_t bm_bytes;
+    uint32_t r4_bytes = 0;
     __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
     __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
     __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
     __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
     __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + kMaxTilesPerItem * 4; }
-    __host__ __device__ constexpr uint32_t bytes() const { return rec_off() + kMaxTilesPerItem * 8; }
+    __host__ __device__ constexpr uint32_t r4_off() const { return rec_off() + kMaxTilesPerItem * 8; }
+    __host__ __device__ constexpr uint32_t bytes() const { return r4_off() + r4_bytes; }
 };
 
 // A text as the kernels see it: coordinates x count bytes from abase, the
@@ -130,6 +140,7 @@ struct ScanParams {
     uint64_t item_cap;           // batch: work items the workspace holds
     uint64_t tiles_per_item;
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
+    uint32_t r4_lds_bytes;       // prefix table bytes the scan kernel stages in LDS (0: the walks start at the root)
     uint64_t *tile_rec;          // records per tile
     uint32_t *tile_nm;           // matched starts per tile
     uint64_t *staging;           // kStageCap per tile: stage_entry() words
@@ -313,13 +324,55 @@ __device__ __forceinline__ uint32_t valid_mask16(const Span &s, uint64_t x) {
     return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
+// 8 text bytes at coordinate z (z >= head; the caller masks bytes past the
+// text).  Built from aligned 8-byte blocks; the second block is read only if
+// it holds a text byte, so both lie in pages the text occupies.
+__device__ __forceinline__ uint64_t text_u64(const Span &s, uint64_t z) {
+    const uint64_t a = z & ~7ull;
+    const uint32_t sh = (uint32_t)(z & 7u) * 8u;
+    const uint64_t lo = *reinterpret_cast<const uint64_t *>(s.abase + a);
+    if (!sh) return lo;
+    const uint64_t hi = a + 8 < s.span_end ? *reinterpret_cast<const uint64_t *>(s.abase + a + 8) : 0ull;
+    return (lo >> sh) | (hi << (64u - sh));
+}
+
+// What a walk reads besides the transition table: the byte classes and the
+// prefix table, both in LDS (the table is null when the dictionary has none,
+// when it is too large for LDS, and in the emit kernel's rare rescans).
+struct WalkTabs {
+    const uint8_t *cls;
+    const uint2 *r4;
+};
+
+// The prefix table's entry for the 4-byte key (0: no pattern begins so).
+__device__ __forceinline__ uint32_t prefix_entry(const GlopDevDict &d, const uint2 *r4, uint32_t key) {
+    const uint32_t mask = (1u << d.r4_lg) - 1u;
+    const uint32_t home = glop_r4_slot(key, d.r4_lg);
+    for (uint32_t i = 0; i <= d.r4_probes; ++i) {
+        const uint2 e = r4[(home + i) & mask];
+        if (e.y == 0u) return 0u;  // an empty slot ends the key's run
+        if (e.x == key) return e.y;
+    }
+    return 0u;
+}
+
 // The failureless walk from coordinate x (Section 5): follow goto edges while
 // they exist; return the deepest terminal state passed (0 = none).  Text bytes
 // come 8 at a time from aligned loads; the walk may run past its tile up to
 // the end of its text.
-__device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, const uint8_t *cls, uint64_t x) {
+__device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, const WalkTabs &tabs, uint64_t x) {
     const uint32_t C = d.num_classes;
     uint32_t st = 0, last = 0;
+    if (tabs.r4) {
+        // The first four steps in one lookup.  Every pattern is at least 4
+        // bytes long and every start leaves room for the shortest, so the
+        // four bytes are text.
+        const uint32_t e = prefix_entry(d, tabs.r4, (uint32_t)text_u64(s, x));
+        if (e == 0u) return 0u;
+        st = e & GLOP_STATE_MASK;
+        if (e & GLOP_TERM_BIT) last = st;
+        x += 4;
+    }
     uint64_t win = 0;
     uint32_t have = 0;
     while (x < s.span_end) {
@@ -337,7 +390,7 @@ __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, co
             win >>= 8 * (x - xa);
             have = 8 - (uint32_t)(x - xa);
         }
-        const uint32_t c = cls[win & 0xFFu];
+        const uint32_t c = tabs.cls[win & 0xFFu];
         win >>= 8;
         --have;
         const uint32_t e = d.delta[(uint64_t)st * C + c];
@@ -347,18 +400,6 @@ __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, co
         ++x;
     }
     return last;
-}
-
-// 8 text bytes at coordinate z (z >= head; the caller masks bytes past the
-// text).  Built from aligned 8-byte blocks; the second block is read only if
-// it holds a text byte, so both lie in pages the text occupies.
-__device__ __forceinline__ uint64_t text_u64(const Span &s, uint64_t z) {
-    const uint64_t a = z & ~7ull;
-    const uint32_t sh = (uint32_t)(z & 7u) * 8u;
-    const uint64_t lo = *reinterpret_cast<const uint64_t *>(s.abase + a);
-    if (!sh) return lo;
-    const uint64_t hi = a + 8 < s.span_end ? *reinterpret_cast<const uint64_t *>(s.abase + a + 8) : 0ull;
-    return (lo >> sh) | (hi << (64u - sh));
 }
 
 // Verify stage of a truncated trie (Sections 2 and 5 complete a truncated
@@ -579,7 +620,7 @@ __device__ __forceinline__ uint32_t popcount(B b) {
 // h's offsets p-3, p-2, p-1, p, so a batch of 16 hits is in offset order.
 template <int TILE, class Sink>
 __device__ __forceinline__ void walk_hit_batch(const ScanParams &P, uint64_t t, const TileInfo &ti,
-                                               const uint8_t *cls, const uint16_t *queue, uint32_t qhead,
+                                               const WalkTabs &tabs, const uint16_t *queue, uint32_t qhead,
                                                uint32_t n, Sink &sink) {
     const uint32_t lane = lane_id();
     const uint32_t h = lane >> 2;
@@ -588,14 +629,14 @@ __device__ __forceinline__ void walk_hit_batch(const ScanParams &P, uint64_t t, 
     const int32_t off = p - 3 + (int32_t)(lane & 3);
     const uint64_t x = ti.x0 + (int64_t)off;
     act = act && off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end;
-    const uint32_t last = act ? walk(P.d, ti.s, cls, x) : 0u;
+    const uint32_t last = act ? walk(P.d, ti.s, tabs, x) : 0u;
     sink.batch(P, t, ti, act ? (uint32_t)off : 0u, last);
 }
 
 // Walk a tile's hit words right away (per-wave ring).
 template <int R, class Sink>
 __device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, const TileInfo &ti, HitBits<R> pbits,
-                                           uint32_t extra_bit, const uint8_t *cls, uint16_t *queue, Sink &sink) {
+                                           uint32_t extra_bit, const WalkTabs &tabs, uint16_t *queue, Sink &sink) {
     constexpr int TILE = R * kRoundBytes;
     const uint32_t lane = lane_id();
     if (__ballot(pbits != 0) != 0 || extra_bit) {
@@ -614,7 +655,7 @@ __device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, cons
             }
             qtail += tot;
             wave_lds_sync();
-            for (; qtail - qhead >= 16u; qhead += 16u) walk_hit_batch<TILE>(P, t, ti, cls, queue, qhead, 16u, sink);
+            for (; qtail - qhead >= 16u; qhead += 16u) walk_hit_batch<TILE>(P, t, ti, tabs, queue, qhead, 16u, sink);
         }
         if (extra_bit) {
             if (lane == 0) queue[qtail & (kRing4 - 1)] = (uint16_t)TILE;
@@ -623,7 +664,7 @@ __device__ __forceinline__ void walk_hits4(const ScanParams &P, uint64_t t, cons
         }
         for (; qtail != qhead;) {
             const uint32_t n = min(16u, qtail - qhead);
-            walk_hit_batch<TILE>(P, t, ti, cls, queue, qhead, n, sink);
+            walk_hit_batch<TILE>(P, t, ti, tabs, queue, qhead, n, sink);
             qhead += n;
         }
     }
@@ -682,7 +723,7 @@ __device__ __forceinline__ bool list_hits(const HitList &L, uint32_t t_rel, HitB
 // particular order (the emit kernel sorts them).
 template <bool BATCH, int TILE>
 __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &L, uint32_t first, uint32_t n,
-                                            uint64_t tb, const uint8_t *cls, uint32_t *nm_l, uint64_t *rec_l,
+                                            uint64_t tb, const WalkTabs &tabs, uint32_t *nm_l, uint64_t *rec_l,
                                             uint32_t *failed) {
     const uint32_t lane = lane_id();
     const uint32_t h = lane >> 2;
@@ -710,7 +751,7 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
         const TileInfo ti = tile_info<BATCH, TILE>(P, t);
         const uint64_t x = ti.x0 + (int64_t)off;
         if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) {
-            last = walk(P.d, ti.s, cls, x);
+            last = walk(P.d, ti.s, tabs, x);
             if (last) nrec = state_records(P.d, ti.s, x, last, pass);
         }
     }
@@ -767,7 +808,7 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
 
 template <int R, class Sink>
 __device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, const TileInfo &ti,
-                                              const uint32_t (&m)[R / 2], const uint8_t *cls, uint16_t *queue,
+                                              const uint32_t (&m)[R / 2], const WalkTabs &tabs, uint16_t *queue,
                                               Sink &sink) {
     const uint32_t lane = lane_id();
     uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
@@ -787,7 +828,7 @@ __device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, c
         wave_lds_sync();
         for (; qtail - qhead >= (uint32_t)kWave; qhead += kWave) {
             const uint32_t off = queue[(qhead + lane) & (kRing1 - 1)];
-            const uint32_t last = walk(P.d, ti.s, cls, ti.x0 + off);
+            const uint32_t last = walk(P.d, ti.s, tabs, ti.x0 + off);
             sink.batch(P, t, ti, off, last);
         }
     }
@@ -795,7 +836,7 @@ __device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, c
         const uint32_t n = qtail - qhead;
         const bool act = lane < n;
         const uint32_t off = act ? queue[(qhead + lane) & (kRing1 - 1)] : 0u;
-        const uint32_t last = act ? walk(P.d, ti.s, cls, ti.x0 + off) : 0u;
+        const uint32_t last = act ? walk(P.d, ti.s, tabs, ti.x0 + off) : 0u;
         sink.batch(P, t, ti, off, last);
     }
     sink.finish(t);
@@ -805,17 +846,17 @@ __device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, c
 // Filter then walk one tile already in registers, walks right away.
 template <int STRIDE, bool FILTER, int K, bool Q4, int R, class Sink>
 __device__ __forceinline__ void scan_loaded_tile(const ScanParams &P, uint64_t t, const TileInfo &ti,
-                                                 const TileRegs<R> &r, const uint32_t *bm, const uint8_t *cls,
+                                                 const TileRegs<R> &r, const uint32_t *bm, const WalkTabs &tabs,
                                                  uint16_t *queue, Sink &sink) {
     if constexpr (STRIDE == 4) {
         HitBits<R> pbits;
         uint32_t xb;
         tile_hits4<R, K, Q4>(P.d, r, bm, pbits, xb);
-        walk_hits4<R>(P, t, ti, pbits, xb, cls, queue, sink);
+        walk_hits4<R>(P, t, ti, pbits, xb, tabs, queue, sink);
     } else {
         uint32_t m[R / 2];
         tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, m);
-        walk_offsets1<R>(P, t, ti, m, cls, queue, sink);
+        walk_offsets1<R>(P, t, ti, m, tabs, queue, sink);
     }
 }
 
@@ -862,7 +903,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     __shared__ uint32_t hl_count, item_failed, tile_next;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
-    const LdsLayout<STRIDE> Lo{P.bm_bytes};
+    const LdsLayout<STRIDE> Lo{P.bm_bytes, P.r4_lds_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -878,6 +919,14 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
              k += (uint64_t)gridDim.x * kBlock)
             P.counts[k] = 0;
     stage_tables<FILTER>(P, bm, cls);
+    const uint2 *r4 = nullptr;
+    if (P.r4_lds_bytes) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.r4);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.r4_off());
+        for (uint32_t k = threadIdx.x; k < P.r4_lds_bytes / 16; k += kBlock) dst[k] = src[k];
+        r4 = reinterpret_cast<const uint2 *>(lds + Lo.r4_off());
+    }
+    const WalkTabs tabs{cls, r4};
 
     const uint64_t nt = total_tiles<BATCH>(P);
     // First work item: a device ticket for a batch, the block index otherwise.
@@ -934,13 +983,13 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 if (has_next) load_tile<R, FILTER, true>(nxt, r);
                 if (__ballot(pbits != 0) != 0 || xb) {
                     if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
-                        walk_hits4<R>(P, t, cur, pbits, xb, cls, queue, sink);
+                        walk_hits4<R>(P, t, cur, pbits, xb, tabs, queue, sink);
                 }
             } else {
                 uint32_t m[R / 2];
                 tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, m);
                 if (has_next) load_tile<R, FILTER>(nxt, r);
-                walk_offsets1<R>(P, t, cur, m, cls, queue, sink);
+                walk_offsets1<R>(P, t, cur, m, tabs, queue, sink);
             }
             cur = nxt;
             c = cn;
@@ -950,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             __syncthreads();
             const uint32_t n = hl_count;
             for (uint32_t f = wave * 16u; f < n; f += kWaves * 16u)
-                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, cls, nm_l, rec_l, &item_failed);
+                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, tabs, nm_l, rec_l, &item_failed);
         }
         __syncthreads();
         // The item's tile results, coalesced, and its total.
@@ -985,6 +1034,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     const LdsLayout<STRIDE> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
+    const WalkTabs tabs{cls, nullptr};
     const uint32_t wave = wave_id();
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
     const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
@@ -1079,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                 TileRegs<R> r;
                 load_tile<R, FILTER>(ti, r);
                 DirectSink sink(&E, over_base[o]);
-                scan_loaded_tile<STRIDE, FILTER, K, Q4, R>(P, ot, ti, r, bm, cls, queue, sink);
+                scan_loaded_tile<STRIDE, FILTER, K, Q4, R>(P, ot, ti, r, bm, tabs, queue, sink);
             }
             __syncthreads();
             base += chunk_total;
@@ -1224,20 +1274,23 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) 
 }
 
 template <int STRIDE>
-constexpr size_t dyn_lds(uint32_t bm_bytes) {
-    return LdsLayout<STRIDE>{bm_bytes}.bytes();
+constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t r4_bytes) {
+    return LdsLayout<STRIDE>{bm_bytes, r4_bytes}.bytes();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R>
 struct Kernels {
     static hipError_t set_lds_limit() {
-        const int bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8);
+        // The scan kernels may stage a prefix table; the emit kernels never do.
+        const int scan_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, r4_lds_cap<STRIDE>());
+        const int emit_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, 0);
         const void *fns[] = {reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>),
                              reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>)};
-        for (const void *f : fns) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        for (int k = 0; k < 4; ++k) {
+            hipError_t e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               k < 2 ? scan_bytes : emit_bytes);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1245,14 +1298,15 @@ struct Kernels {
 
     static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
                           const glop_events_t *ev) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.r4_lds_bytes);
+        const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
         hipError_t e;
         if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
         hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && ev->scan_end && (e = hipEventRecord((hipEvent_t)ev->scan_end, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P,
-                           E);
+        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), emit_lds, s,
+                           P, E);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && ev->emit_end) e = hipEventRecord((hipEvent_t)ev->emit_end, s);
         return e;
@@ -1260,7 +1314,8 @@ struct Kernels {
 
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes);
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.r4_lds_bytes);
+        const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);
         const uint64_t items = (P.tile_cap + P.tiles_per_item - 1) / P.tiles_per_item;
@@ -1273,7 +1328,8 @@ struct Kernels {
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>), dim3(cus), dim3(kBlock), lds, s, P);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>), dim3(cus), dim3(kBlock), lds, s, P, E);
+        hipLaunchKernelGGL((glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>), dim3(cus), dim3(kBlock), emit_lds, s, P,
+                           E);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const uint32_t fb = (P.nchunks + 255) / 256 > 1024 ? 1024u : (uint32_t)((P.nchunks + 255) / 256);
         hipLaunchKernelGGL(glop_batch_finish_kernel<0>, dim3(fb ? fb : 1), dim3(256), 0, s, P, E.chunk_first,

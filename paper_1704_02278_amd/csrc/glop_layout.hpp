@@ -23,6 +23,18 @@
 // word g, zero above q bytes) set bit glop_slot1(g) and, with two probe bits,
 // also bit glop_slot2(g).  A text position whose q-gram misses any of its bits
 // cannot be where any pattern's t-th q-gram sits.
+//
+// Prefix table: when every pattern (as the trie holds it) is at least 4 bytes
+// long, so that no pattern ends above depth 4, an exact hash table maps each
+// pattern's first 4 bytes (little-endian 32-bit key) to the delta entry of the
+// depth-4 state they reach (state | GLOP_TERM_BIT if it ends a pattern).  A
+// walk begins with one lookup there instead of four dependent table steps, and
+// a start whose first 4 bytes begin no pattern ends at that lookup (the scan
+// kernel uses the table when it fits in LDS).  The table
+// has 2^r4_lg slots of (key, entry) with entry 0 marking an empty slot; a key's
+// home slot is glop_r4_slot(key), a key whose home is taken sits in the next
+// free slot (linear probing), and no key sits more than r4_probes slots past
+// its home.
 #pragma once
 #include <stdint.h>
 
@@ -56,6 +68,10 @@ GLOP_HD uint32_t glop_slot2(uint32_t g, uint32_t bitmap_log2) { return glop_hash
 GLOP_HD uint32_t glop_block_word(uint32_t h, uint32_t bitmap_log2) { return h >> (37u - bitmap_log2); }
 GLOP_HD uint32_t glop_block_bits(uint32_t h) { return (1u << ((h >> 8) & 31u)) | (1u << ((h >> 13) & 31u)); }
 
+// Home slot of a prefix-table key: Knuth's multiplicative hash (the golden
+// ratio times 2^32), top r4_lg bits.
+GLOP_HD uint32_t glop_r4_slot(uint32_t key, uint32_t r4_lg) { return (key * 0x9E3779B1u) >> (32u - r4_lg); }
+
 struct GlopDevDict {
     const uint32_t *delta;   // num_states * num_classes
     const uint32_t *term;    // 2 * num_states: (first, count) per state
@@ -74,4 +90,7 @@ struct GlopDevDict {
     const uint8_t *pat_bytes;  // all patterns back to back
     const uint64_t *pat_off;   // first byte of pattern j in pat_bytes
     const uint32_t *pat_len;   // length of pattern j
+    // Prefix table (null when some pattern is shorter than 4 bytes).
+    const uint32_t *r4;        // 2^r4_lg slots of (key, entry)
+    uint32_t r4_lg, r4_probes;
 };

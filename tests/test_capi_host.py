@@ -85,6 +85,23 @@ def test_state_count_is_distinct_prefixes_plus_root():
     assert info["filter"] == glop.GLOP_FILTER_QGRAM and info["stride"] == 4 and info["qgram"] == 4
 
 
+def test_prefix_table_holds_the_distinct_four_byte_prefixes():
+    """The walk's first four steps come from an exact table of the patterns'
+    4-byte prefixes; it exists only when no pattern is shorter than 4 bytes."""
+    pats = synth.gen_patterns(synth.WORKLOADS["medium"].patterns, 5, 77)
+    info = host_dict(pats).info()
+    keys = {p[:4] for p in pats}
+    assert info["prefix_keys"] == len(keys)
+    slots = info["prefix_slots"]
+    assert slots >= 2 * len(keys) and slots & (slots - 1) == 0 and slots >= 64
+    short = host_dict(pats + [b"abc"]).info()
+    assert short["prefix_keys"] == 0 and short["prefix_slots"] == 0
+    # Patterns of exactly 4 bytes end on the table's own states; a longer
+    # pattern through one of them adds no key.
+    four = host_dict([b"GET ", b"POST", b"GET /x"]).info()
+    assert four["prefix_keys"] == 2 and four["prefix_slots"] == 64
+
+
 def test_automatic_options():
     assert host_dict([b"abcdefg"]).info()["stride"] == 4
     assert host_dict([b"abcdef"]).info()["stride"] == 1

@@ -156,3 +156,26 @@ def test_dense_hits_at_stride4_fill_the_workgroup_list():
         d = glop.Dict(pats, **opts)
         assert d.info()["stride"] == 4
         assert_same(gpu_match(d, t), want, f"dense stride4 {opts}")
+
+
+@pytest.mark.parametrize("n_pats,lo,hi", [(1500, 7, 12), (3000, 7, 12), (900, 4, 6), (1500, 4, 6)])
+def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
+    # The scan kernel uses the 4-byte prefix table when it fits in LDS (up to
+    # 4,096 slots at stride 4, 2,048 at stride 1) and starts its walks at the
+    # root otherwise; these dictionaries land on both sides of both limits.
+    # A 16-letter alphabet makes most offsets start some pattern's first bytes.
+    rng = np.random.default_rng(n_pats * 31 + lo)
+    alpha = np.frombuffer(b"etaoinshrdlucmfw", dtype=np.uint8)
+    pats = [bytes(alpha[rng.integers(0, 16, size=int(L))]) for L in rng.integers(lo, hi + 1, size=n_pats)]
+    text = alpha[rng.integers(0, 16, size=3 << 20)]
+    text[::97] = 0x0A  # lines, which the planter keeps occurrences inside
+    assert len(synth.plant(text, pats, 2048, seed=5, stream_id=9)) > 1000
+    want = oracle_match(text, pats)
+    info = glop.Dict(pats).info()
+    keys = len({p[:4] for p in pats})
+    assert info["prefix_keys"] == keys
+    say("prefix-table", n_pats, lo, hi, info["prefix_slots"], info["stride"], want[3])
+    t = to_device(text, shift=5)
+    for opts in variants_for(pats):
+        say("prefix-table", n_pats, opts)
+        assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"prefix table {n_pats} {opts}")
