@@ -320,9 +320,10 @@ typedef struct {
     uint32_t candidates;     /* 1 if unverified prefix candidates are reported */
     uint64_t device_bytes;   /* device memory held by the handle */
     int32_t device;          /* HIP device id, or -1 for a host-only handle */
-    uint32_t prefix_keys;    /* distinct 4-byte pattern prefixes in the prefix table
-                                (0: no table, some pattern is shorter than 4 bytes) */
+    uint32_t prefix_keys;    /* distinct prefix_depth-byte pattern prefixes in the prefix
+                                table (0: no table, some pattern is shorter than 4 bytes) */
     uint32_t prefix_slots;   /* slots of the prefix table (a power of two, or 0) */
+    uint32_t prefix_depth;   /* 8 if every pattern is at least 8 bytes, else 4 (or 0) */
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 

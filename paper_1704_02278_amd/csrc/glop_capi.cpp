@@ -82,8 +82,8 @@ int upload(glop_dict *h) {
     const uint64_t o_pbytes = align256(o_out + (c.outids.size() + 1) * 4);
     const uint64_t o_poff = align256(o_pbytes + c.pat_bytes.size());
     const uint64_t o_plen = align256(o_poff + c.pat_off.size() * 8);
-    const uint64_t o_r4 = align256(o_plen + c.pat_len.size() * 4);
-    const uint64_t bytes = align256(o_r4 + c.r4.size() * 4);
+    const uint64_t o_pt = align256(o_plen + c.pat_len.size() * 4);
+    const uint64_t bytes = align256(o_pt + c.pt.size() * 4);
     void *blob = nullptr;
     e = hipMalloc(&blob, bytes);
     if (e != hipSuccess) return fail(GLOP_ENOMEM, std::string("hipMalloc of the dictionary: ") + hipGetErrorString(e));
@@ -100,7 +100,7 @@ int upload(glop_dict *h) {
                   {o_pbytes, c.pat_bytes.data(), c.pat_bytes.size()},
                   {o_poff, c.pat_off.data(), c.pat_off.size() * 8},
                   {o_plen, c.pat_len.data(), c.pat_len.size() * 4},
-                  {o_r4, c.r4.data(), c.r4.size() * 4}};
+                  {o_pt, c.pt.data(), c.pt.size() * 4}};
     for (const Piece &p : pieces) {
         if (!p.n) continue;
         e = hipMemcpy(b + p.off, p.src, p.n, hipMemcpyHostToDevice);
@@ -135,9 +135,11 @@ int upload(glop_dict *h) {
     d.pat_bytes = c.verifies() ? b + o_pbytes : nullptr;
     d.pat_off = c.verifies() ? reinterpret_cast<const uint64_t *>(b + o_poff) : nullptr;
     d.pat_len = c.verifies() ? reinterpret_cast<const uint32_t *>(b + o_plen) : nullptr;
-    d.r4 = c.r4.empty() ? nullptr : reinterpret_cast<const uint32_t *>(b + o_r4);
-    d.r4_lg = c.r4_lg;
-    d.r4_probes = c.r4_probes;
+    d.pt = c.pt.empty() ? nullptr : reinterpret_cast<const uint32_t *>(b + o_pt);
+    d.pt_lg = c.pt_lg;
+    d.pt_probes = c.pt_probes;
+    d.pt_depth = c.pt_depth;
+    d.pt_leaf = c.pt_leaf;
     return GLOP_OK;
 }
 
@@ -763,8 +765,9 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->candidates = c.candidates;
     out->device_bytes = h->blob_bytes;
     out->device = h->blob ? h->device : -1;
-    out->prefix_keys = c.r4_keys;
-    out->prefix_slots = c.r4.empty() ? 0u : (1u << c.r4_lg);
+    out->prefix_keys = c.pt_keys;
+    out->prefix_slots = c.pt.empty() ? 0u : (1u << c.pt_lg);
+    out->prefix_depth = c.pt_depth;
     return ok();
 }
 

@@ -81,9 +81,9 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
     P.bm_bytes = d.filter == GLOP_FILTER_QGRAM ? (1u << d.bitmap_log2) / 8 : 0u;
     // The prefix table is used when it fits in LDS beside the rest of the scan
     // kernel's layout (stride-4 layout for the stride-4 filter, else stride 1).
-    const uint32_t r4_bytes = d.r4 ? (8u << d.r4_lg) : 0u;
-    const uint32_t r4_cap = d.filter == GLOP_FILTER_QGRAM && d.stride == 4 ? r4_lds_cap<4>() : r4_lds_cap<1>();
-    P.r4_lds_bytes = r4_bytes <= r4_cap ? r4_bytes : 0u;
+    const uint32_t pt_bytes = d.pt ? (16u << d.pt_lg) : 0u;
+    const uint32_t pt_cap = d.filter == GLOP_FILTER_QGRAM && d.stride == 4 ? pt_lds_cap<4>() : pt_lds_cap<1>();
+    P.pt_lds_bytes = pt_bytes <= pt_cap ? pt_bytes : 0u;
     P.counts = counts;
     return P;
 }

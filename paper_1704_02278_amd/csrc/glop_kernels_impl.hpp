@@ -91,7 +91,7 @@ constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
 // global memory costs about what the first steps through the transition
 // table's hot root rows cost (measured slower on a 20,000-pattern dictionary).
 template <int STRIDE>
-constexpr uint32_t r4_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
+constexpr uint32_t pt_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
 
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
 // per-tile matched-start counts | per-tile record counts | prefix table (scan
@@ -99,14 +99,14 @@ constexpr uint32_t r4_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
 template <int STRIDE>
 struct LdsLayout {
     uint32_t bm_bytes;
-    uint32_t r4_bytes = 0;
+    uint32_t pt_bytes = 0;
     __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
     __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
     __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
     __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
     __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + kMaxTilesPerItem * 4; }
-    __host__ __device__ constexpr uint32_t r4_off() const { return rec_off() + kMaxTilesPerItem * 8; }
-    __host__ __device__ constexpr uint32_t bytes() const { return r4_off() + r4_bytes; }
+    __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + kMaxTilesPerItem * 8; }
+    __host__ __device__ constexpr uint32_t bytes() const { return pt_off() + pt_bytes; }
 };
 
 // A text as the kernels see it: coordinates x count bytes from abase, the
@@ -140,7 +140,7 @@ struct ScanParams {
     uint64_t item_cap;           // batch: work items the workspace holds
     uint64_t tiles_per_item;
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
-    uint32_t r4_lds_bytes;       // prefix table bytes the scan kernel stages in LDS (0: the walks start at the root)
+    uint32_t pt_lds_bytes;       // prefix table bytes the scan kernel stages in LDS (0: the walks start at the root)
     uint64_t *tile_rec;          // records per tile
     uint32_t *tile_nm;           // matched starts per tile
     uint64_t *staging;           // kStageCap per tile: stage_entry() words
@@ -341,17 +341,18 @@ __device__ __forceinline__ uint64_t text_u64(const Span &s, uint64_t z) {
 // when it is too large for LDS, and in the emit kernel's rare rescans).
 struct WalkTabs {
     const uint8_t *cls;
-    const uint2 *r4;
+    const uint4 *pt;
 };
 
-// The prefix table's entry for the 4-byte key (0: no pattern begins so).
-__device__ __forceinline__ uint32_t prefix_entry(const GlopDevDict &d, const uint2 *r4, uint32_t key) {
-    const uint32_t mask = (1u << d.r4_lg) - 1u;
-    const uint32_t home = glop_r4_slot(key, d.r4_lg);
-    for (uint32_t i = 0; i <= d.r4_probes; ++i) {
-        const uint2 e = r4[(home + i) & mask];
-        if (e.y == 0u) return 0u;  // an empty slot ends the key's run
-        if (e.x == key) return e.y;
+// The prefix table's entry for a key (0: no pattern begins so); one 16-byte
+// read per slot.
+__device__ __forceinline__ uint32_t prefix_entry(const GlopDevDict &d, const uint4 *pt, uint32_t lo, uint32_t hi) {
+    const uint32_t mask = (1u << d.pt_lg) - 1u;
+    const uint32_t home = glop_pt_slot(lo, hi, d.pt_lg);
+    for (uint32_t i = 0; i <= d.pt_probes; ++i) {
+        const uint4 e = pt[(home + i) & mask];
+        if (e.z == 0u) return 0u;  // an empty slot ends the key's run
+        if (e.x == lo && e.y == hi) return e.z;
     }
     return 0u;
 }
@@ -363,15 +364,17 @@ __device__ __forceinline__ uint32_t prefix_entry(const GlopDevDict &d, const uin
 __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, const WalkTabs &tabs, uint64_t x) {
     const uint32_t C = d.num_classes;
     uint32_t st = 0, last = 0;
-    if (tabs.r4) {
-        // The first four steps in one lookup.  Every pattern is at least 4
-        // bytes long and every start leaves room for the shortest, so the
-        // four bytes are text.
-        const uint32_t e = prefix_entry(d, tabs.r4, (uint32_t)text_u64(s, x));
+    if (tabs.pt) {
+        // The first D steps in one lookup.  Every pattern is at least D bytes
+        // long and every start leaves room for the shortest, so the D bytes
+        // are text, and no pattern ends above depth D.
+        const uint64_t w = text_u64(s, x);
+        const uint32_t e = prefix_entry(d, tabs.pt, (uint32_t)w, d.pt_depth == 8 ? (uint32_t)(w >> 32) : 0u);
         if (e == 0u) return 0u;
         st = e & GLOP_STATE_MASK;
         if (e & GLOP_TERM_BIT) last = st;
-        x += 4;
+        if (d.pt_leaf) return last;
+        x += d.pt_depth;
     }
     uint64_t win = 0;
     uint32_t have = 0;
@@ -903,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     __shared__ uint32_t hl_count, item_failed, tile_next;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
-    const LdsLayout<STRIDE> Lo{P.bm_bytes, P.r4_lds_bytes};
+    const LdsLayout<STRIDE> Lo{P.bm_bytes, P.pt_lds_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -919,14 +922,14 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
              k += (uint64_t)gridDim.x * kBlock)
             P.counts[k] = 0;
     stage_tables<FILTER>(P, bm, cls);
-    const uint2 *r4 = nullptr;
-    if (P.r4_lds_bytes) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.r4);
-        uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.r4_off());
-        for (uint32_t k = threadIdx.x; k < P.r4_lds_bytes / 16; k += kBlock) dst[k] = src[k];
-        r4 = reinterpret_cast<const uint2 *>(lds + Lo.r4_off());
+    const uint4 *pt = nullptr;
+    if (P.pt_lds_bytes) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.pt);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.pt_off());
+        for (uint32_t k = threadIdx.x; k < P.pt_lds_bytes / 16; k += kBlock) dst[k] = src[k];
+        pt = reinterpret_cast<const uint4 *>(lds + Lo.pt_off());
     }
-    const WalkTabs tabs{cls, r4};
+    const WalkTabs tabs{cls, pt};
 
     const uint64_t nt = total_tiles<BATCH>(P);
     // First work item: a device ticket for a batch, the block index otherwise.
@@ -1274,15 +1277,15 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) 
 }
 
 template <int STRIDE>
-constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t r4_bytes) {
-    return LdsLayout<STRIDE>{bm_bytes, r4_bytes}.bytes();
+constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes) {
+    return LdsLayout<STRIDE>{bm_bytes, pt_bytes}.bytes();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R>
 struct Kernels {
     static hipError_t set_lds_limit() {
         // The scan kernels may stage a prefix table; the emit kernels never do.
-        const int scan_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, r4_lds_cap<STRIDE>());
+        const int scan_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, pt_lds_cap<STRIDE>());
         const int emit_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, 0);
         const void *fns[] = {reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>),
@@ -1298,7 +1301,7 @@ struct Kernels {
 
     static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
                           const glop_events_t *ev) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.r4_lds_bytes);
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.pt_lds_bytes);
         const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
         hipError_t e;
         if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
@@ -1314,7 +1317,7 @@ struct Kernels {
 
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.r4_lds_bytes);
+        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.pt_lds_bytes);
         const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);

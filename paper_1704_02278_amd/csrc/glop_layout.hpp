@@ -24,17 +24,19 @@
 // also bit glop_slot2(g).  A text position whose q-gram misses any of its bits
 // cannot be where any pattern's t-th q-gram sits.
 //
-// Prefix table: when every pattern (as the trie holds it) is at least 4 bytes
-// long, so that no pattern ends above depth 4, an exact hash table maps each
-// pattern's first 4 bytes (little-endian 32-bit key) to the delta entry of the
-// depth-4 state they reach (state | GLOP_TERM_BIT if it ends a pattern).  A
-// walk begins with one lookup there instead of four dependent table steps, and
-// a start whose first 4 bytes begin no pattern ends at that lookup (the scan
-// kernel uses the table when it fits in LDS).  The table
-// has 2^r4_lg slots of (key, entry) with entry 0 marking an empty slot; a key's
-// home slot is glop_r4_slot(key), a key whose home is taken sits in the next
-// free slot (linear probing), and no key sits more than r4_probes slots past
-// its home.
+// Prefix table: when every pattern (as the trie holds it) is at least D bytes
+// long, D = 8 if it can be and 4 otherwise (none below 4), an exact hash table
+// maps each distinct D-byte pattern prefix (little-endian 64-bit key, zero
+// above D bytes) to the delta entry of the depth-D state it reaches (state |
+// GLOP_TERM_BIT if it ends a pattern).  No pattern ends above depth D, so a
+// walk may begin with one lookup there instead of D dependent table steps, and
+// a start whose first D bytes begin no pattern ends at that lookup; when the
+// trie is cut at depth D (pt_leaf) the lookup is the whole walk.  The scan
+// kernel uses the table when it fits in LDS.  The table has 2^pt_lg slots of
+// four words (key low, key high, entry, 0) with entry 0 marking an empty slot;
+// a key's home slot is glop_pt_slot(key), a key whose home is taken sits in
+// the next free slot (linear probing), and no key sits more than pt_probes
+// slots past its home.
 #pragma once
 #include <stdint.h>
 
@@ -68,9 +70,12 @@ GLOP_HD uint32_t glop_slot2(uint32_t g, uint32_t bitmap_log2) { return glop_hash
 GLOP_HD uint32_t glop_block_word(uint32_t h, uint32_t bitmap_log2) { return h >> (37u - bitmap_log2); }
 GLOP_HD uint32_t glop_block_bits(uint32_t h) { return (1u << ((h >> 8) & 31u)) | (1u << ((h >> 13) & 31u)); }
 
-// Home slot of a prefix-table key: Knuth's multiplicative hash (the golden
-// ratio times 2^32), top r4_lg bits.
-GLOP_HD uint32_t glop_r4_slot(uint32_t key, uint32_t r4_lg) { return (key * 0x9E3779B1u) >> (32u - r4_lg); }
+// Home slot of a prefix-table key: the high word folded into the low one,
+// then Knuth's multiplicative hash (the golden ratio times 2^32), top pt_lg
+// bits.
+GLOP_HD uint32_t glop_pt_slot(uint32_t lo, uint32_t hi, uint32_t pt_lg) {
+    return ((lo ^ (hi * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32u - pt_lg);
+}
 
 struct GlopDevDict {
     const uint32_t *delta;   // num_states * num_classes
@@ -91,6 +96,8 @@ struct GlopDevDict {
     const uint64_t *pat_off;   // first byte of pattern j in pat_bytes
     const uint32_t *pat_len;   // length of pattern j
     // Prefix table (null when some pattern is shorter than 4 bytes).
-    const uint32_t *r4;        // 2^r4_lg slots of (key, entry)
-    uint32_t r4_lg, r4_probes;
+    const uint32_t *pt;        // 2^pt_lg slots of (key low, key high, entry, 0)
+    uint32_t pt_lg, pt_probes;
+    uint32_t pt_depth;         // D: 4 or 8
+    uint32_t pt_leaf;          // 1 if the trie ends at depth D (the lookup is the walk)
 };

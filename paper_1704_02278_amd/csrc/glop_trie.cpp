@@ -23,48 +23,55 @@ uint32_t ceil_log2(uint64_t v) {
     return k;
 }
 
-// The exact table of the patterns' 4-byte prefixes (layout in
-// glop_layout.hpp), from the finished transition table: every path of four
-// edges from the root spells one prefix.  Byte classes are one per pattern
-// byte, so a class path names its bytes.
-void build_prefix_table(Compiled &c) {
+// The exact table of the patterns' D-byte prefixes (layout in
+// glop_layout.hpp), from the finished transition table: every path of D edges
+// from the root spells one prefix.  Byte classes are one per pattern byte, so
+// a class path names its bytes.
+void build_prefix_table(Compiled &c, uint32_t D) {
     const uint32_t C = c.num_classes;
     uint8_t byte_of[256] = {};
     for (int b = 0; b < 256; ++b)
         if (c.cls[b]) byte_of[c.cls[b]] = (uint8_t)b;
     struct Node {
-        uint32_t state, key, depth;
+        uint32_t state, depth;
+        uint64_t key;
     };
-    std::vector<Node> todo{{0u, 0u, 0u}};
-    std::vector<std::pair<uint32_t, uint32_t>> keys;  // (key, entry)
+    std::vector<Node> todo{{0u, 0u, 0ull}};
+    std::vector<std::pair<uint64_t, uint32_t>> keys;  // (key, entry)
     while (!todo.empty()) {
         const Node f = todo.back();
         todo.pop_back();
         for (uint32_t k = 1; k < C; ++k) {
             const uint32_t e = c.delta[(uint64_t)f.state * C + k];
             if (!e) continue;
-            const uint32_t key = f.key | ((uint32_t)byte_of[k] << (8 * f.depth));
-            if (f.depth == 3)
+            const uint64_t key = f.key | ((uint64_t)byte_of[k] << (8 * f.depth));
+            if (f.depth + 1 == D)
                 keys.emplace_back(key, e);
             else
-                todo.push_back({e & GLOP_STATE_MASK, key, f.depth + 1});
+                todo.push_back({e & GLOP_STATE_MASK, f.depth + 1, key});
         }
     }
     const uint32_t lg = std::max<uint32_t>(6, ceil_log2(2ull * keys.size()));  // at most half full
     const uint32_t mask = (1u << lg) - 1u;
-    c.r4.assign(2ull << lg, 0u);
+    c.pt.assign(4ull << lg, 0u);
     uint32_t far = 0;
     for (const auto &kv : keys) {
-        const uint32_t home = glop_r4_slot(kv.first, lg);
+        const uint32_t lo = (uint32_t)kv.first, hi = (uint32_t)(kv.first >> 32);
+        const uint32_t home = glop_pt_slot(lo, hi, lg);
         uint32_t d = 0;
-        while (c.r4[2 * ((home + d) & mask) + 1] != 0) ++d;
-        c.r4[2 * ((home + d) & mask)] = kv.first;
-        c.r4[2 * ((home + d) & mask) + 1] = kv.second;
+        while (c.pt[4 * ((home + d) & mask) + 2] != 0) ++d;
+        uint32_t *slot = &c.pt[4 * ((home + d) & mask)];
+        slot[0] = lo;
+        slot[1] = hi;
+        slot[2] = kv.second;
         far = std::max(far, d);
     }
-    c.r4_lg = lg;
-    c.r4_probes = far;
-    c.r4_keys = (uint32_t)keys.size();
+    c.pt_lg = lg;
+    c.pt_probes = far;
+    c.pt_keys = (uint32_t)keys.size();
+    c.pt_depth = D;
+    // Cut at depth D: no state below it, so the lookup ends every walk.
+    c.pt_leaf = c.prefix_len == D ? 1u : 0u;
 }
 
 uint32_t load_qgram(const uint8_t *p, uint32_t q) {
@@ -353,7 +360,7 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
             for (uint32_t j = 0; j < n; ++j) std::memcpy(c.pat_bytes.data() + c.pat_off[j], patterns[j], lengths[j]);
         }
 
-        if (c.min_len >= 4) build_prefix_table(c);
+        if (c.min_len >= 4) build_prefix_table(c, c.min_len >= 8 ? 8u : 4u);
         const int rc = build_filter(patterns, n, o, c, err);
         if (rc != GLOP_OK) return rc;
     } catch (const std::bad_alloc &) {

@@ -28,9 +28,10 @@ struct Compiled {
     std::vector<uint8_t> pat_bytes;   // verification copy of the patterns, back to back
     std::vector<uint64_t> pat_off;
     std::vector<uint32_t> pat_len;
-    // Exact table of the 4-byte prefixes (empty when some pattern is shorter).
-    std::vector<uint32_t> r4;  // 2^r4_lg slots of (key, entry)
-    uint32_t r4_lg = 0, r4_probes = 0, r4_keys = 0;
+    // Exact table of the D-byte prefixes (empty when some pattern is shorter
+    // than 4 bytes; layout in glop_layout.hpp).
+    std::vector<uint32_t> pt;  // 2^pt_lg slots of 4 words
+    uint32_t pt_lg = 0, pt_probes = 0, pt_keys = 0, pt_depth = 0, pt_leaf = 0;
     bool verifies() const { return prefix_len && !candidates; }
 };
 

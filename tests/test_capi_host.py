@@ -85,21 +85,27 @@ def test_state_count_is_distinct_prefixes_plus_root():
     assert info["filter"] == glop.GLOP_FILTER_QGRAM and info["stride"] == 4 and info["qgram"] == 4
 
 
-def test_prefix_table_holds_the_distinct_four_byte_prefixes():
-    """The walk's first four steps come from an exact table of the patterns'
-    4-byte prefixes; it exists only when no pattern is shorter than 4 bytes."""
+def test_prefix_table_holds_the_distinct_prefixes():
+    """The walk's first D steps come from an exact table of the patterns'
+    D-byte prefixes: D = 8 when every pattern is at least 8 bytes long, else 4;
+    no table when some pattern is shorter than 4 bytes."""
     pats = synth.gen_patterns(synth.WORKLOADS["medium"].patterns, 5, 77)
+    assert min(map(len, pats)) >= 8
     info = host_dict(pats).info()
-    keys = {p[:4] for p in pats}
-    assert info["prefix_keys"] == len(keys)
+    assert info["prefix_depth"] == 8 and info["prefix_keys"] == len({p[:8] for p in pats})
     slots = info["prefix_slots"]
-    assert slots >= 2 * len(keys) and slots & (slots - 1) == 0 and slots >= 64
+    assert slots >= 2 * info["prefix_keys"] and slots & (slots - 1) == 0 and slots >= 64
+    mid = host_dict(pats + [b"abcdefg"]).info()
+    assert mid["prefix_depth"] == 4 and mid["prefix_keys"] == len({p[:4] for p in pats + [b"abcdefg"]})
     short = host_dict(pats + [b"abc"]).info()
-    assert short["prefix_keys"] == 0 and short["prefix_slots"] == 0
+    assert short["prefix_keys"] == 0 and short["prefix_slots"] == 0 and short["prefix_depth"] == 0
     # Patterns of exactly 4 bytes end on the table's own states; a longer
     # pattern through one of them adds no key.
     four = host_dict([b"GET ", b"POST", b"GET /x"]).info()
-    assert four["prefix_keys"] == 2 and four["prefix_slots"] == 64
+    assert four["prefix_depth"] == 4 and four["prefix_keys"] == 2 and four["prefix_slots"] == 64
+    # The whole-pattern trie keys on the same prefixes (its walks go on below).
+    full = host_dict(pats, prefix_len=glop.GLOP_PREFIX_FULL).info()
+    assert full["prefix_depth"] == 8 and full["prefix_keys"] == info["prefix_keys"]
 
 
 def test_automatic_options():

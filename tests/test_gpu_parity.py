@@ -158,12 +158,15 @@ def test_dense_hits_at_stride4_fill_the_workgroup_list():
         assert_same(gpu_match(d, t), want, f"dense stride4 {opts}")
 
 
-@pytest.mark.parametrize("n_pats,lo,hi", [(1500, 7, 12), (3000, 7, 12), (900, 4, 6), (1500, 4, 6)])
+@pytest.mark.parametrize("n_pats,lo,hi", [(900, 8, 14), (2500, 8, 14), (900, 7, 12), (1500, 7, 12),
+                                           (450, 4, 6), (900, 4, 6)])
 def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
-    # The scan kernel uses the 4-byte prefix table when it fits in LDS (up to
-    # 4,096 slots at stride 4, 2,048 at stride 1) and starts its walks at the
-    # root otherwise; these dictionaries land on both sides of both limits.
-    # A 16-letter alphabet makes most offsets start some pattern's first bytes.
+    # The scan kernel uses the prefix table (8-byte keys when every pattern
+    # has 8 bytes, else 4-byte keys) when it fits in LDS: up to 2,048 slots at
+    # stride 4, 1,024 at stride 1, at most half full; otherwise its walks start
+    # at the root.  These dictionaries land on both sides of both limits, with
+    # both key lengths.  A 16-letter alphabet makes most offsets start some
+    # pattern's first bytes.
     rng = np.random.default_rng(n_pats * 31 + lo)
     alpha = np.frombuffer(b"etaoinshrdlucmfw", dtype=np.uint8)
     pats = [bytes(alpha[rng.integers(0, 16, size=int(L))]) for L in rng.integers(lo, hi + 1, size=n_pats)]
@@ -172,8 +175,8 @@ def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
     assert len(synth.plant(text, pats, 2048, seed=5, stream_id=9)) > 1000
     want = oracle_match(text, pats)
     info = glop.Dict(pats).info()
-    keys = len({p[:4] for p in pats})
-    assert info["prefix_keys"] == keys
+    depth = 8 if lo >= 8 else 4
+    assert info["prefix_depth"] == depth and info["prefix_keys"] == len({p[:depth] for p in pats})
     say("prefix-table", n_pats, lo, hi, info["prefix_slots"], info["stride"], want[3])
     t = to_device(text, shift=5)
     for opts in variants_for(pats):
