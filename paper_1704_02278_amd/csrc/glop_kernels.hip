@@ -156,7 +156,7 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     // Items small enough that every CU gets work, one tile per wave at least.
     const uint64_t cus = (uint64_t)(a.num_cus > 0 ? a.num_cus : 1);
     uint64_t per = (g.tile_cap + cus - 1) / cus;
-    per = per < kMinBatchTilesPerItem ? kMinBatchTilesPerItem : (per > kMaxTilesPerItem ? kMaxTilesPerItem : per);
+    per = per < kMinBatchTilesPerItem ? kMinBatchTilesPerItem : (per > kMaxBatchTilesPerItem ? kMaxBatchTilesPerItem : per);
     P.tiles_per_item = per;
     uint8_t *ws = static_cast<uint8_t *>(a.workspace);
     P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);
@@ -171,12 +171,11 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
 }
 
 hipError_t launch_stream_read(const uint8_t *data, uint64_t len, uint64_t *sink, int num_cus, hipStream_t stream) {
-    // The single-text scan's item split: one item per CU, at most 512 tiles each.
+    // The single-text scan's item split.
     const uint64_t n16 = len / 16, ntiles = (n16 + 8 * kWave - 1) / (8 * kWave);
     if (ntiles == 0) return hipSuccess;
     const uint64_t cus = (uint64_t)(num_cus > 0 ? num_cus : 1);
-    uint64_t tpi = (ntiles + cus - 1) / cus;
-    if (tpi > kMaxTilesPerItem) tpi = kMaxTilesPerItem;
+    const uint64_t tpi = single_tiles_per_item(ntiles, cus);
     const uint32_t grid = (uint32_t)((ntiles + tpi - 1) / tpi);
     hipLaunchKernelGGL(glop_stream_read_kernel, dim3(grid), dim3(kBlock), 0, stream, data, n16, tpi, sink);
     return hipGetLastError();

@@ -35,7 +35,7 @@
 //          and written directly.
 //
 // One text is split statically: workgroup g owns work item g (a run of up to
-// 512 tiles).  A batch of chunks is first laid out as one list of tiles (each
+// 1024 tiles).  A batch of chunks is first laid out as one list of tiles (each
 // chunk starts a new tile; a prep kernel scans the chunk table and maps every
 // tile to its chunk), and the scan workgroups stay resident and take work
 // items from a device ticket until none is left.
@@ -67,10 +67,23 @@ constexpr uint32_t kRing4 = 512;
 constexpr uint32_t kHitCap = 8192;
 constexpr uint32_t kHitFree = 0xFFFFFFFFu;
 constexpr uint32_t kPosBits = 15;
-// Tiles per work item at most (per-tile result counters live in LDS), and at
-// least for a batch (one tile per wave).
-constexpr uint32_t kMaxTilesPerItem = 512;
+// Tiles per work item at most (per-tile result counters live in LDS: 12 KiB).
+// Every item ends in a phase without HBM reads (the deferred walks, the tile
+// results), so long items pay it less often; a batch's items, handed out
+// from a ticket, stay at 512 tiles or less (with longer ones the last items
+// left CUs idle), and at least one tile per wave.
+constexpr uint32_t kMaxTilesPerItem = 1024;
+constexpr uint32_t kMaxBatchTilesPerItem = 512;
 constexpr uint32_t kMinBatchTilesPerItem = 16;
+
+// A single text's split: the fewest rounds of one item per CU whose items stay
+// within kMaxTilesPerItem, items of equal size (so no round runs a few
+// stragglers alone).
+__host__ __device__ constexpr uint64_t single_tiles_per_item(uint64_t ntiles, uint64_t cus) {
+    const uint64_t rounds = ntiles ? (ntiles + cus * kMaxTilesPerItem - 1) / (cus * kMaxTilesPerItem) : 1;
+    const uint64_t items = cus * rounds;
+    return ntiles ? (ntiles + items - 1) / items : 1;
+}
 
 // Batch metadata words in the workspace.
 enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaError = 5, kMetaWords = 8 };
@@ -93,10 +106,16 @@ constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
 template <int STRIDE>
 constexpr uint32_t pt_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
 
+// Tile counters a work item holds in LDS: a batch's items are shorter, and
+// its kernels keep the smaller layout (sized for 1024 tiles, the batched scan
+// measured 10 % slower).
+template <bool BATCH>
+constexpr uint32_t item_tiles_cap() { return BATCH ? kMaxBatchTilesPerItem : kMaxTilesPerItem; }
+
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
 // per-tile matched-start counts | per-tile record counts | prefix table (scan
 // kernel, when staged).
-template <int STRIDE>
+template <int STRIDE, bool BATCH>
 struct LdsLayout {
     uint32_t bm_bytes;
     uint32_t pt_bytes = 0;
@@ -104,8 +123,8 @@ struct LdsLayout {
     __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
     __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
     __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
-    __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + kMaxTilesPerItem * 4; }
-    __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + kMaxTilesPerItem * 8; }
+    __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + item_tiles_cap<BATCH>() * 4; }
+    __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + item_tiles_cap<BATCH>() * 8; }
     __host__ __device__ constexpr uint32_t bytes() const { return pt_off() + pt_bytes; }
 };
 
@@ -888,9 +907,9 @@ __device__ __forceinline__ uint64_t total_items(const ScanParams &P) {
 }
 
 // Clear a work item's LDS tile counters (and hit list at stride 4).
-template <bool DEFER>
+template <bool DEFER, bool BATCH>
 __device__ __forceinline__ void reset_item_lds(uint32_t *nm_l, uint64_t *rec_l, uint32_t *hits) {
-    for (uint32_t k = threadIdx.x; k < kMaxTilesPerItem; k += kBlock) {
+    for (uint32_t k = threadIdx.x; k < item_tiles_cap<BATCH>(); k += kBlock) {
         nm_l[k] = 0;
         rec_l[k] = 0;
     }
@@ -906,7 +925,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     __shared__ uint32_t hl_count, item_failed, tile_next;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
-    const LdsLayout<STRIDE> Lo{P.bm_bytes, P.pt_lds_bytes};
+    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -945,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         tile_next = 0;
         if (kDefer) hl_count = 0;
     }
-    reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
+    reset_item_lds<kDefer, BATCH>(nm_l, rec_l, HL.hits);
     // A wave takes the item's next tile from an LDS counter whenever it starts
     // one, so all 16 waves keep loads in flight until the item's last tile (a
     // fixed share per wave left some waves idle for a fifth of the item while
@@ -1021,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             tile_next = 0;
             if (kDefer) hl_count = 0;
         }
-        reset_item_lds<kDefer>(nm_l, rec_l, HL.hits);
+        reset_item_lds<kDefer, BATCH>(nm_l, rec_l, HL.hits);
     }
 }
 
@@ -1034,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     __shared__ uint32_t n_over, any_over, any_failed;
     __shared__ uint64_t over_tile[kBlock];
     __shared__ uint64_t over_base[kBlock];
-    const LdsLayout<STRIDE> Lo{P.bm_bytes};
+    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const WalkTabs tabs{cls, nullptr};
@@ -1244,8 +1263,7 @@ inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile) {
     Geometry g{};
     g.ntiles = (len + 15 + tile - 1) / tile;  // the text plus up to 15 leading alignment bytes
     const uint64_t wgs = (uint64_t)(num_cus > 0 ? num_cus : 1);
-    g.tiles_per_item = g.ntiles ? (g.ntiles + wgs - 1) / wgs : 1;
-    if (g.tiles_per_item > kMaxTilesPerItem) g.tiles_per_item = kMaxTilesPerItem;
+    g.tiles_per_item = single_tiles_per_item(g.ntiles, wgs);
     g.grid = (uint32_t)(g.ntiles ? (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item : 0);
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.ntiles * 8);
@@ -1276,24 +1294,25 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) 
     return g;
 }
 
-template <int STRIDE>
+template <int STRIDE, bool BATCH>
 constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes) {
-    return LdsLayout<STRIDE>{bm_bytes, pt_bytes}.bytes();
+    return LdsLayout<STRIDE, BATCH>{bm_bytes, pt_bytes}.bytes();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R>
 struct Kernels {
     static hipError_t set_lds_limit() {
         // The scan kernels may stage a prefix table; the emit kernels never do.
-        const int scan_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, pt_lds_cap<STRIDE>());
-        const int emit_bytes = (int)dyn_lds<STRIDE>((1u << 19) / 8, 0);
+        constexpr uint32_t bm = (1u << 19) / 8;
+        const int bytes[4] = {(int)dyn_lds<STRIDE, false>(bm, pt_lds_cap<STRIDE>()),
+                              (int)dyn_lds<STRIDE, true>(bm, pt_lds_cap<STRIDE>()), (int)dyn_lds<STRIDE, false>(bm, 0),
+                              (int)dyn_lds<STRIDE, true>(bm, 0)};
         const void *fns[] = {reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>),
                              reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, true>)};
         for (int k = 0; k < 4; ++k) {
-            hipError_t e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               k < 2 ? scan_bytes : emit_bytes);
+            hipError_t e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[k]);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -1301,8 +1320,8 @@ struct Kernels {
 
     static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
                           const glop_events_t *ev) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.pt_lds_bytes);
-        const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
+        const size_t lds = dyn_lds<STRIDE, false>(P.bm_bytes, P.pt_lds_bytes);
+        const size_t emit_lds = dyn_lds<STRIDE, false>(P.bm_bytes, 0);
         hipError_t e;
         if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
         hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P);
@@ -1317,8 +1336,8 @@ struct Kernels {
 
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
-        const size_t lds = dyn_lds<STRIDE>(P.bm_bytes, P.pt_lds_bytes);
-        const size_t emit_lds = dyn_lds<STRIDE>(P.bm_bytes, 0);
+        const size_t lds = dyn_lds<STRIDE, true>(P.bm_bytes, P.pt_lds_bytes);
+        const size_t emit_lds = dyn_lds<STRIDE, true>(P.bm_bytes, 0);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);
         const uint64_t items = (P.tile_cap + P.tiles_per_item - 1) / P.tiles_per_item;
