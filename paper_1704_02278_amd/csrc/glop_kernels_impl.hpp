@@ -458,30 +458,43 @@ __device__ __forceinline__ bool verified(const GlopDevDict &d, const Span &s, ui
     return true;
 }
 
-// Records at coordinate x of a walk whose deepest terminal is st.  With a
-// verify stage, `pass` receives which of the first 16 listed patterns passed
-// (bit k for the k-th), valid when the list has at most 16 entries.
-__device__ __forceinline__ uint32_t state_records(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t st,
-                                                  uint32_t &pass) {
-    const uint32_t cnt = d.term[2 * st + 1];
-    pass = 0;
-    if (!d.verify_from) return cnt;
-    const uint32_t first = d.term[2 * st];
-    uint32_t n = 0;
-    for (uint32_t k = 0; k < cnt; ++k) {
-        const bool ok = verified(d, s, x, d.outids[first + k]);
-        n += ok ? 1u : 0u;
-        if (ok && k < 16) pass |= 1u << k;
+// Records at coordinate x of a walk whose deepest terminal is st: the listed
+// patterns that match (all of them without a verify stage, those whose rest
+// follows in the text with one), and which of the first 16 do (`pass`, bit k
+// for the k-th; complete when the list has at most 16 entries).
+struct StateRecords {
+    uint32_t n;       // records: listed patterns that match here
+    uint32_t first;   // the state's output list: outids[first .. first + listed)
+    uint32_t listed;
+    uint32_t pass;    // bit k: listed pattern k matches (k < 16)
+};
+
+__device__ __forceinline__ StateRecords state_records(const GlopDevDict &d, const Span &s, uint64_t x, uint32_t st) {
+    const uint2 tl = *reinterpret_cast<const uint2 *>(d.term + 2 * st);  // (first, count), one load
+    StateRecords r{tl.y, tl.x, tl.y, 0u};
+    if (!d.verify_from) {
+        r.pass = tl.y <= 16 ? (1u << tl.y) - 1u : 0u;
+        return r;
     }
-    return n;
+    r.n = 0;
+    for (uint32_t k = 0; k < tl.y; ++k) {
+        const bool ok = verified(d, s, x, d.outids[tl.x + k]);
+        r.n += ok ? 1u : 0u;
+        if (ok && k < 16) r.pass |= 1u << k;
+    }
+    return r;
 }
 
 // A staged matched start, ordered by its offset in the tile (top 15 bits):
-// offset << 49 | pass-mask-valid << 48 | pass mask << 32 | deepest terminal.
-// The mask (state_records) spares the emit kernel a second verification.
-__device__ __forceinline__ uint64_t stage_entry(const GlopDevDict &d, uint32_t off, uint32_t st, uint32_t pass) {
-    const uint64_t valid = (d.verify_from && d.term[2 * st + 1] <= 16) ? 1ull : 0ull;
-    return ((uint64_t)off << 49) | (valid << 48) | ((uint64_t)(pass & 0xFFFFu) << 32) | st;
+// offset << 49 | list-form << 48 | pass mask << 32 | low word.  With at most
+// 16 listed patterns (list form) the low word is the output list's first
+// index and the mask names the records, so the emit kernel reads neither the
+// state's list bounds nor, after a verify stage, a single pattern byte again;
+// otherwise the low word is the deepest terminal state.
+__device__ __forceinline__ uint64_t stage_entry(uint32_t off, uint32_t st, const StateRecords &r) {
+    const bool list = r.listed <= 16;
+    return ((uint64_t)off << 49) | ((uint64_t)(list ? 1u : 0u) << 48) | ((uint64_t)(r.pass & 0xFFFFu) << 32) |
+           (list ? r.first : st);
 }
 
 // Where tile t lies: its text (or chunk), its first coordinate, and whether
@@ -551,13 +564,14 @@ struct StageSink {
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
-        uint32_t pass = 0;
-        const uint32_t cnt = last ? state_records(P.d, ti.s, ti.x0 + off, last, pass) : 0u;
+        StateRecords sr{0u, 0u, 0u, 0u};
+        if (last) sr = state_records(P.d, ti.s, ti.x0 + off, last);
+        const uint32_t cnt = sr.n;
         const bool m = cnt != 0;
         const uint64_t bal = __ballot(m);
         if (bal == 0) return;
         const uint32_t pos = nm + (uint32_t)__popcll(bal & lanemask_lt());
-        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = stage_entry(P.d, off, last, pass);
+        if (m && pos < kStageCap) P.staging[t * kStageCap + pos] = stage_entry(off, last, sr);
         nm += (uint32_t)__popcll(bal);
         rec += wave_sum_u32(cnt);
     }
@@ -580,8 +594,7 @@ struct DirectSink {
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
         const uint64_t x = ti.x0 + off;
-        uint32_t pass = 0;
-        const uint32_t cnt = last ? state_records(P.d, ti.s, x, last, pass) : 0u;
+        const uint32_t cnt = last ? state_records(P.d, ti.s, x, last).n : 0u;
         const bool m = cnt != 0;
         if (__ballot(m) == 0) return;
         uint32_t tot;
@@ -768,19 +781,20 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
     const uint32_t t_rel = ent >> kPosBits;
     const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
     const uint64_t t = tb + t_rel;
-    uint32_t last = 0, nrec = 0, pass = 0;
+    uint32_t last = 0;
+    StateRecords sr{0u, 0u, 0u, 0u};
     if (act) {
         const TileInfo ti = tile_info<BATCH, TILE>(P, t);
         const uint64_t x = ti.x0 + (int64_t)off;
         if (off >= 0 && off < TILE && x >= ti.s.head && x < ti.s.valid_end) {
             last = walk(P.d, ti.s, tabs, x);
-            if (last) nrec = state_records(P.d, ti.s, x, last, pass);
+            if (last) sr = state_records(P.d, ti.s, x, last);
         }
     }
-    if (nrec) {
+    if (sr.n) {
         const uint32_t slot = atomicAdd(&nm_l[t_rel], 1u);
-        if (slot < kStageCap) P.staging[t * kStageCap + slot] = stage_entry(P.d, (uint32_t)off, last, pass);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)nrec);
+        if (slot < kStageCap) P.staging[t * kStageCap + slot] = stage_entry((uint32_t)off, last, sr);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&rec_l[t_rel]), (unsigned long long)sr.n);
     }
 }
 
@@ -1090,6 +1104,8 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         uint32_t over = 0;
         for (uint64_t t = tb + threadIdx.x; t < te; t += kBlock) over |= P.tile_nm[t] > kStageCap;
         if (over) atomicOr(&any_over, 1u);
+        // The first block of tile record counts, read beside the sums above.
+        const uint64_t rec0 = tb + threadIdx.x < te ? P.tile_rec[tb + threadIdx.x] : 0ull;
         uint64_t base = call_base + block_sum_u64(part, red);  // its barriers publish any_over
         if (any_over && !staged) {
             stage_tables<FILTER>(P, bm, cls);
@@ -1100,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         for (uint64_t c0 = tb; c0 < te; c0 += kBlock) {
             const uint64_t t = c0 + threadIdx.x;
             const bool in = t < te;
-            const uint64_t rec = in ? P.tile_rec[t] : 0ull;
+            const uint64_t rec = c0 == tb ? rec0 : (in ? P.tile_rec[t] : 0ull);
             uint64_t chunk_total;
             const uint64_t tile_base = base + block_excl_scan_u64(rec, scan_sh, chunk_total);
             if (threadIdx.x == 0) n_over = 0;
@@ -1126,20 +1142,29 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                             if ((e == 0 || c > prev) && c < ent) ent = c;
                         }
                         prev = ent;
-                        const uint32_t st = (uint32_t)ent;
+                        const uint32_t low = (uint32_t)ent;
                         const uint64_t x = ti.x0 + (ent >> 49);
-                        const bool have_mask = (ent >> 48) & 1u;
-                        const uint32_t pass = (uint32_t)(ent >> 32) & 0xFFFFu;
                         const uint64_t i = x - ti.s.head + E.offset_add;
-                        const uint32_t first = P.d.term[2 * st], cnt = P.d.term[2 * st + 1];
-                        for (uint32_t k = 0; k < cnt; ++k) {
-                            const uint32_t id = P.d.outids[first + k];
-                            if (P.d.verify_from &&
-                                !(have_mask ? ((pass >> k) & 1u) != 0 : verified(P.d, ti.s, x, id)))
-                                continue;
-                            if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
-                            atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
-                            ++pos;
+                        if ((ent >> 48) & 1u) {
+                            // List form: the mask names the records, in list order.
+                            uint32_t bits = (uint32_t)(ent >> 32) & 0xFFFFu;
+                            while (bits) {
+                                const uint32_t k = (uint32_t)__builtin_ctz(bits);
+                                bits &= bits - 1u;
+                                const uint32_t id = P.d.outids[low + k];
+                                if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
+                                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                                ++pos;
+                            }
+                        } else {
+                            const uint32_t first = P.d.term[2 * low], cnt = P.d.term[2 * low + 1];
+                            for (uint32_t k = 0; k < cnt; ++k) {
+                                const uint32_t id = P.d.outids[first + k];
+                                if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
+                                if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
+                                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                                ++pos;
+                            }
                         }
                     }
                 }
