@@ -321,8 +321,9 @@ __device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32
     if (!Q4) g &= qmask;
     if (K == 3) {
         const uint32_t h = glop_hash1(g);
-        const uint32_t m = glop_block_bits(h);
-        return (bm[h >> (sh + 5u)] & m) == m ? 1u : 0u;
+        // Both bits set, written as "no bit of the pair missing" so the two
+        // one-bit masks feed a single three-input logic op.
+        return (~bm[h >> (sh + 5u)] & glop_block_bits(h)) == 0u ? 1u : 0u;
     }
     const uint32_t s1 = glop_hash1(g) >> sh;
     uint32_t hit = bm[s1 >> 5] >> (s1 & 31);
