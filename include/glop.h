@@ -344,7 +344,11 @@ uint32_t glop_max_len(glop_handle_t h);
  * into one glop_match_batch launch (a lone request takes the single-text
  * kernels), up to max_batch_requests requests and max_batch_bytes bytes, and
  * as far as the HBM budget allows.  Requests that
- * arrive while batches run join the next launch.  The paper streams batches
+ * arrive while batches run join the next launch.  The scheduler polls its
+ * in-flight launches without sleeping (and for 2 ms after its last progress),
+ * and glop_server_poll spins for up to 2 ms before it sleeps: a small
+ * request's GPU time is about 20 us, far less than a thread's wake-up, so a
+ * busy server keeps one host core busy.  The paper streams batches
  * of logs through the device so transfers overlap matching (Section 6) and
  * names real-time operation as future work (Section 8); this is that
  * operation for many concurrent streams.

@@ -29,6 +29,16 @@ int64_t now_ns() {
 
 constexpr uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
+// Waiting without sleeping: a small call's GPU time is 20 µs or less, while a
+// condition-variable sleep costs tens of microseconds to wake from (and a
+// short timed wait oversleeps by the kernel's timer slack, 50 µs by default).
+// So the scheduler polls its in-flight batches, and keeps polling for a while
+// after its last progress, with the lock released between polls; a poller
+// spins on the completion count before it sleeps.  This keeps one host core
+// busy while requests are in flight.
+constexpr int64_t kSchedSpinNs = 2000000;  // scheduler: poll until 2 ms without progress
+constexpr int64_t kPollSpinNs = 2000000;   // poller: spin up to 2 ms, then sleep
+
 uint64_t out_capacity(uint64_t len) { return std::max<uint64_t>(64, len / 256); }
 
 struct Request {
@@ -90,6 +100,7 @@ struct glop_server {
     std::deque<Request> fifo;                  // plain mode: all requests in arrival order
     std::deque<Inflight> inflight;             // launch order
     std::deque<glop_completion_t> done;
+    std::atomic<uint64_t> done_total{0};       // completions ever queued (read without the lock)
     std::unordered_map<uint64_t, Held> held;   // completed, not yet released
     std::vector<Slot> slots;
     hipStream_t free_stream = nullptr;
@@ -168,7 +179,10 @@ struct glop_server {
             inflight.erase(inflight.begin() + fi);
             any = true;
         }
-        if (any) cv_done.notify_all();
+        if (any) {
+            done_total.store(done_total.load(std::memory_order_relaxed) + 1, std::memory_order_release);
+            cv_done.notify_all();
+        }
         return any;
     }
 
@@ -332,6 +346,7 @@ struct glop_server {
     void run() {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
+        int64_t last_progress = now_ns();
         for (;;) {
             bool progress = reap_locked();
             if (stop) {
@@ -357,11 +372,16 @@ struct glop_server {
                 progress = true;
             }
             if (stop && outstanding == 0 && inflight.empty()) break;
-            if (!progress) {
-                if (inflight.empty())
-                    cv_work.wait_for(lk, std::chrono::milliseconds(2));
-                else
-                    cv_work.wait_for(lk, std::chrono::microseconds(10));
+            const int64_t t = now_ns();
+            if (progress) {
+                last_progress = t;
+            } else if (!inflight.empty() || t - last_progress < kSchedSpinNs) {
+                // Poll again soon; submitters and pollers take the lock meanwhile.
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                cv_work.wait_for(lk, std::chrono::milliseconds(2));
             }
         }
     }
@@ -467,8 +487,20 @@ int glop_server_submit(glop_server_t s, uint32_t dict, const uint8_t *d_text, ui
 int glop_server_poll(glop_server_t s, glop_completion_t *out, uint32_t max, uint32_t wait_us, uint32_t *n) {
     if (!s || !n || (max > 0 && !out)) return GLOP_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
-    if (s->done.empty() && wait_us > 0)
-        s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [s] { return !s->done.empty(); });
+    if (s->done.empty() && wait_us > 0) {
+        // Spin on the completion count first (see kPollSpinNs), then sleep.
+        const uint64_t seen = s->done_total.load(std::memory_order_acquire);
+        const int64_t t0 = now_ns(), deadline = t0 + (int64_t)wait_us * 1000;
+        lk.unlock();
+        int64_t t = t0;
+        while (s->done_total.load(std::memory_order_acquire) == seen && t < deadline && t - t0 < kPollSpinNs) {
+            std::this_thread::yield();
+            t = now_ns();
+        }
+        lk.lock();
+        if (s->done.empty() && t < deadline)
+            s->cv_done.wait_for(lk, std::chrono::nanoseconds(deadline - t), [s] { return !s->done.empty(); });
+    }
     uint32_t k = 0;
     while (k < max && !s->done.empty()) {
         out[k++] = s->done.front();
