@@ -224,7 +224,10 @@ typedef struct {
 /*
  * glop_match with caller-provided device workspace and an optional total.
  *
- *   d_total      device pointer to one uint64 receiving |M| (may be NULL).
+ *   d_total      pointer to one uint64 receiving |M| (may be NULL): device
+ *                memory, or pinned host memory (hipHostMalloc), which the
+ *                emit kernel then writes directly, visible to the host once
+ *                the stream has completed the call.
  *   d_workspace  device pointer, 256-byte aligned, at least
  *                glop_workspace_bytes(h, len) bytes; owned by the caller, who
  *                must not use it for anything else until the stream has

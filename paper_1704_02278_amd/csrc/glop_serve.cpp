@@ -307,14 +307,12 @@ struct glop_server {
         f.single = true;
         f.launch_ns = now_ns();
         const Request &r = f.reqs[0];
+        // The total goes straight to the slot's pinned word (no copy back).
         int rc = glop_match_ws(dicts[dict], r.len ? r.text : nullptr, r.len, f.out, cap,
-                               reinterpret_cast<uint64_t *>(b + o_counts), reinterpret_cast<uint64_t *>(b + o_total),
-                               b + o_ws, ws_bytes, sl.stream, nullptr);
+                               reinterpret_cast<uint64_t *>(b + o_counts), sl.h_res, b + o_ws, ws_bytes, sl.stream,
+                               nullptr);
         hipError_t e = hipSuccess;
-        if (rc == GLOP_OK &&
-            ((e = hipMemcpyAsync(sl.h_res, b + o_total, 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
-             (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess))
-            rc = GLOP_EHIP;
+        if (rc == GLOP_OK && (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) rc = GLOP_EHIP;
         if (rc != GLOP_OK) set_error(rc, std::string("launch failed: ") + glop_last_error_message());
         sl.busy = true;
         inflight.push_back(std::move(f));

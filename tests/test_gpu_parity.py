@@ -182,3 +182,24 @@ def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
     for opts in variants_for(pats):
         say("prefix-table", n_pats, opts)
         assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"prefix table {n_pats} {opts}")
+
+
+def test_total_written_to_pinned_host_memory():
+    # glop_match_ws may take a pinned host word for the total: the emit kernel
+    # writes it directly (the server's single-request path relies on this).
+    pats, text, _ = synth.make_workload("medium", n_bytes=6 << 20)
+    want = oracle_match(text, pats)
+    d = glop.Dict(pats)
+    t = to_device(text)
+    out = torch.empty((want[3] + 64, 2), dtype=torch.int64, device="cuda")
+    counts = torch.empty(len(pats), dtype=torch.int64, device="cuda")
+    ws = torch.empty(d.workspace_bytes(t.numel()) + 256, dtype=torch.uint8, device="cuda")
+    ws = ws[(-ws.data_ptr()) % 256:][:d.workspace_bytes(t.numel())]
+    host_total = torch.full((1,), -1, dtype=torch.int64).pin_memory()
+    for k in range(3):
+        say("pinned total", k)
+        host_total.fill_(-1)
+        d.match_into(t, out, counts, total=host_total, workspace=ws)
+        torch.cuda.synchronize()
+        assert int(host_total[0]) == want[3]
+    assert np.array_equal(out[:want[3], 0].cpu().numpy().astype(np.uint64), want[0])
