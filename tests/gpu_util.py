@@ -21,6 +21,9 @@ def variants_for(patterns):
     out = [dict()]
     if patterns:
         minlen = min(len(p) for p in patterns)
+        if max(len(p) for p in patterns) > 8:
+            # The whole-pattern trie: walks go on below the prefix table's depth.
+            out.append(dict(prefix_len=glop.GLOP_PREFIX_FULL))
         out.append(dict(filter=glop.GLOP_FILTER_NONE))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=1))
