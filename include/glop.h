@@ -327,6 +327,8 @@ typedef struct {
                                 table (0: no table, some pattern is shorter than 4 bytes) */
     uint32_t prefix_slots;   /* slots of the prefix table (a power of two, or 0) */
     uint32_t prefix_depth;   /* 8 if every pattern is at least 8 bytes, else 4 (or 0) */
+    uint32_t filter2_log2;   /* bits (log2) of the second filter checked before
+                                stride-1 walks, or 0 when there is none */
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 

@@ -92,6 +92,7 @@ class glop_info_t(ctypes.Structure):
         ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
         ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
         ("prefix_keys", ctypes.c_uint32), ("prefix_slots", ctypes.c_uint32), ("prefix_depth", ctypes.c_uint32),
+        ("filter2_log2", ctypes.c_uint32),
     ]
 
 

@@ -83,7 +83,8 @@ int upload(glop_dict *h) {
     const uint64_t o_poff = align256(o_pbytes + c.pat_bytes.size());
     const uint64_t o_plen = align256(o_poff + c.pat_off.size() * 8);
     const uint64_t o_pt = align256(o_plen + c.pat_len.size() * 4);
-    const uint64_t bytes = align256(o_pt + c.pt.size() * 4);
+    const uint64_t o_bm2 = align256(o_pt + c.pt.size() * 4);
+    const uint64_t bytes = align256(o_bm2 + c.bitmap2.size() * 4);
     void *blob = nullptr;
     e = hipMalloc(&blob, bytes);
     if (e != hipSuccess) return fail(GLOP_ENOMEM, std::string("hipMalloc of the dictionary: ") + hipGetErrorString(e));
@@ -100,7 +101,8 @@ int upload(glop_dict *h) {
                   {o_pbytes, c.pat_bytes.data(), c.pat_bytes.size()},
                   {o_poff, c.pat_off.data(), c.pat_off.size() * 8},
                   {o_plen, c.pat_len.data(), c.pat_len.size() * 4},
-                  {o_pt, c.pt.data(), c.pt.size() * 4}};
+                  {o_pt, c.pt.data(), c.pt.size() * 4},
+                  {o_bm2, c.bitmap2.data(), c.bitmap2.size() * 4}};
     for (const Piece &p : pieces) {
         if (!p.n) continue;
         e = hipMemcpy(b + p.off, p.src, p.n, hipMemcpyHostToDevice);
@@ -136,6 +138,7 @@ int upload(glop_dict *h) {
     d.pat_off = c.verifies() ? reinterpret_cast<const uint64_t *>(b + o_poff) : nullptr;
     d.pat_len = c.verifies() ? reinterpret_cast<const uint32_t *>(b + o_plen) : nullptr;
     d.pt = c.pt.empty() ? nullptr : reinterpret_cast<const uint32_t *>(b + o_pt);
+    d.bitmap2 = c.bitmap2.empty() ? nullptr : reinterpret_cast<const uint32_t *>(b + o_bm2);
     d.pt_lg = c.pt_lg;
     d.pt_probes = c.pt_probes;
     d.pt_depth = c.pt_depth;
@@ -278,6 +281,7 @@ struct TuneRun {
     uint64_t *counts = nullptr;
     uint64_t *total = nullptr;
     uint32_t *bitmap = nullptr;  // largest filter bitmap (2^19 bits)
+    uint32_t *bitmap2 = nullptr; // second filter (a candidate's own keys)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     uint64_t expect = ~0ull;     // match count every option set must give
     uint32_t evaluated = 0;
@@ -285,7 +289,7 @@ struct TuneRun {
     ~TuneRun() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        for (void *p : {ws, (void *)out, (void *)counts, (void *)total, (void *)bitmap})
+        for (void *p : {ws, (void *)out, (void *)counts, (void *)total, (void *)bitmap, (void *)bitmap2})
             if (p) (void)hipFree(p);
         if (h) glop_free(h);
         if (alt) glop_free(alt);
@@ -298,7 +302,8 @@ struct TuneRun {
         if ((e = hipMalloc(&ws, ws_bytes)) != hipSuccess || (e = hipMalloc((void **)&out, cap * 16)) != hipSuccess ||
             (e = hipMalloc((void **)&counts, (uint64_t)std::max<uint32_t>(n, 1) * 8)) != hipSuccess ||
             (e = hipMalloc((void **)&total, 8)) != hipSuccess ||
-            (e = hipMalloc((void **)&bitmap, (1u << 19) / 8)) != hipSuccess)
+            (e = hipMalloc((void **)&bitmap, (1u << 19) / 8)) != hipSuccess ||
+            (e = hipMalloc((void **)&bitmap2, (1u << GLOP_FILTER2_LOG2) / 8)) != hipSuccess)
             return fail(GLOP_ENOMEM, std::string("hipMalloc while tuning: ") + hipGetErrorString(e));
         if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
             return hip_fail(e, "hipEventCreate");
@@ -329,11 +334,14 @@ struct TuneRun {
         o.prefix_len = hd->c.prefix_len ? hd->c.prefix_len : GLOP_PREFIX_FULL;
         o.candidates = 0;
         hipError_t e = hipMemcpyAsync(bitmap, f.bitmap.data(), f.bitmap.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !f.bitmap2.empty())
+            e = hipMemcpyAsync(bitmap2, f.bitmap2.data(), f.bitmap2.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "bitmap upload while tuning");
         glop::MatchLaunch a{};
         a.d = hd->dd;
         a.d.bitmap = bitmap;
+        a.d.bitmap2 = f.bitmap2.empty() ? nullptr : bitmap2;
         a.d.filter = f.filter;
         a.d.qgram = f.qgram;
         a.d.qmask = f.qmask;
@@ -768,6 +776,7 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->prefix_keys = c.pt_keys;
     out->prefix_slots = c.pt.empty() ? 0u : (1u << c.pt_lg);
     out->prefix_depth = c.pt_depth;
+    out->filter2_log2 = c.bitmap2.empty() ? 0u : GLOP_FILTER2_LOG2;
     return ok();
 }
 

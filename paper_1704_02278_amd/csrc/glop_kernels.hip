@@ -84,6 +84,11 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
     const uint32_t pt_bytes = d.pt ? (16u << d.pt_lg) : 0u;
     const uint32_t pt_cap = d.filter == GLOP_FILTER_QGRAM && d.stride == 4 ? pt_lds_cap<4>() : pt_lds_cap<1>();
     P.pt_lds_bytes = pt_bytes <= pt_cap ? pt_bytes : 0u;
+    // The second filter takes the prefix table's place when that is not
+    // staged (the two never fit together; it is built for stride 1 only).
+    P.f2_lds_bytes = d.bitmap2 && !P.pt_lds_bytes && d.filter == GLOP_FILTER_QGRAM && d.stride == 1
+                         ? (1u << GLOP_FILTER2_LOG2) / 8
+                         : 0u;
     P.counts = counts;
     return P;
 }

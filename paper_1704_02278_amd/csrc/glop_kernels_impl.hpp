@@ -57,13 +57,15 @@ constexpr int kBlock = kWave * kWaves;      // 1024 threads
 constexpr int kRoundBytes = kWave * 16;     // 1 KiB: 16 bytes per lane
 constexpr uint32_t kMinTileBytes = 8 * kRoundBytes;
 constexpr uint32_t kStageCap = 16;          // staged matched starts per tile
-// Per-wave LDS rings (u16 entries).  Stride 1 queues offsets: at most 63 left
-// over plus 1024 from one round.  Stride 4 queues hit words: at most 15 left
-// over plus 256 from one round plus the word after the tile.
-constexpr uint32_t kRing1 = 2048;
+// Per-wave LDS rings (u16 entries) for tiles walked at once.  Stride 1 queues
+// offsets half a round at a time: at most 63 left over plus 512.  Stride 4
+// queues hit words: at most 15 left over plus 256 from one round plus the word
+// after the tile.
+constexpr uint32_t kRing1 = 1024;
 constexpr uint32_t kRing4 = 512;
-// Deferred hit list (stride 4): entry = tile index in the item << 15 | word
-// position in the tile (0 .. tile bytes); unwritten slots hold kHitFree.
+// Deferred hit list (both strides): entry = tile index in the item << 15 |
+// position in the tile (stride 4: a hit word's, stride 1: a surviving
+// offset's); unwritten slots hold kHitFree.
 constexpr uint32_t kHitCap = 8192;
 constexpr uint32_t kHitFree = 0xFFFFFFFFu;
 constexpr uint32_t kPosBits = 15;
@@ -105,6 +107,8 @@ constexpr uint32_t ring_cap() { return STRIDE == 4 ? kRing4 : kRing1; }
 // table's hot root rows cost (measured slower on a 20,000-pattern dictionary).
 template <int STRIDE>
 constexpr uint32_t pt_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
+// The second filter (stride 1) uses the prefix table's room.
+static_assert((1u << GLOP_FILTER2_LOG2) / 8 <= pt_lds_cap<1>(), "second filter exceeds its LDS room");
 
 // Tile counters a work item holds in LDS: a batch's items are shorter, and
 // its kernels keep the smaller layout (sized for 1024 tiles, the batched scan
@@ -113,19 +117,21 @@ template <bool BATCH>
 constexpr uint32_t item_tiles_cap() { return BATCH ? kMaxBatchTilesPerItem : kMaxTilesPerItem; }
 
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
-// per-tile matched-start counts | per-tile record counts | prefix table (scan
-// kernel, when staged).
+// per-tile matched-start counts | per-tile record counts | prefix table or
+// second filter (scan kernel, when staged; never both).
 template <int STRIDE, bool BATCH>
 struct LdsLayout {
     uint32_t bm_bytes;
     uint32_t pt_bytes = 0;
+    uint32_t f2_bytes = 0;
     __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
     __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
     __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
-    __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + (STRIDE == 4 ? kHitCap * 4 : 0); }
+    __host__ __device__ constexpr uint32_t nm_off() const { return hits_off() + kHitCap * 4; }
     __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + item_tiles_cap<BATCH>() * 4; }
     __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + item_tiles_cap<BATCH>() * 8; }
-    __host__ __device__ constexpr uint32_t bytes() const { return pt_off() + pt_bytes; }
+    __host__ __device__ constexpr uint32_t f2_off() const { return pt_off() + pt_bytes; }
+    __host__ __device__ constexpr uint32_t bytes() const { return f2_off() + f2_bytes; }
 };
 
 // A text as the kernels see it: coordinates x count bytes from abase, the
@@ -160,6 +166,7 @@ struct ScanParams {
     uint64_t tiles_per_item;
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
     uint32_t pt_lds_bytes;       // prefix table bytes the scan kernel stages in LDS (0: the walks start at the root)
+    uint32_t f2_lds_bytes;       // second filter bytes the scan kernel stages in LDS (0: none)
     uint64_t *tile_rec;          // records per tile
     uint32_t *tile_nm;           // matched starts per tile
     uint64_t *staging;           // kStageCap per tile: stage_entry() words
@@ -757,12 +764,14 @@ __device__ __forceinline__ bool list_hits(const HitList &L, uint32_t t_rel, HitB
 // Walk n listed hit words from index `first` (n <= 16).  Matched starts claim
 // their tile's staging slots with LDS atomics, so a tile's slots are in no
 // particular order (the emit kernel sorts them).
-template <bool BATCH, int TILE>
+// PER = starts per entry: 4 for a stride-4 hit word (lanes 4h..4h+3 take its
+// four candidate starts), 1 for a stride-1 offset (a lane per entry).
+template <bool BATCH, int TILE, int PER>
 __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &L, uint32_t first, uint32_t n,
                                             uint64_t tb, const WalkTabs &tabs, uint32_t *nm_l, uint64_t *rec_l,
                                             uint32_t *failed) {
     const uint32_t lane = lane_id();
-    const uint32_t h = lane >> 2;
+    const uint32_t h = PER == 4 ? lane >> 2 : lane;
     bool act = h < n;
     uint32_t ent = 0;
     if (act) {
@@ -780,7 +789,8 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
         }
     }
     const uint32_t t_rel = ent >> kPosBits;
-    const int32_t off = (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3);
+    const int32_t off = PER == 4 ? (int32_t)(ent & ((1u << kPosBits) - 1u)) - 3 + (int32_t)(lane & 3)
+                                 : (int32_t)(ent & ((1u << kPosBits) - 1u));
     const uint64_t t = tb + t_rel;
     uint32_t last = 0;
     StateRecords sr{0u, 0u, 0u, 0u};
@@ -799,13 +809,54 @@ __device__ __forceinline__ void walk_listed(const ScanParams &P, const HitList &
     }
 }
 
+// Record every offset of tile t that survived the filters (bit u of round k's
+// mask is offset k*1024 + lane*16 + u) in the list; false if they do not all
+// fit (then the tile must be walked right away).  Reserved as in list_hits.
+template <int R>
+__device__ __forceinline__ bool list_offsets1(const HitList &L, uint32_t t_rel, const uint32_t (&m)[R / 2]) {
+    const uint32_t lane = lane_id();
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) c += (uint32_t)__popc(m[k]);
+    uint32_t tot;
+    const uint32_t pre = wave_prefix_small<8>(c, tot);  // c <= 16 * R = 128
+    if (tot == 0) return true;
+    uint32_t base = 0, ok = 0;
+    if (lane == 0) {
+        uint32_t cur = __hip_atomic_load(L.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        while (cur + tot <= kHitCap) {
+            const uint32_t prev = atomicCAS(L.count, cur, cur + tot);
+            if (prev == cur) {
+                base = cur;
+                ok = 1;
+                break;
+            }
+            cur = prev;
+        }
+    }
+    if (!__builtin_amdgcn_readfirstlane(ok)) return false;
+    uint32_t pos = __builtin_amdgcn_readfirstlane(base) + pre;
+    const uint32_t tag = t_rel << kPosBits;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+        const uint32_t at = (uint32_t)k * kRoundBytes + lane * 16u;
+        while (mask) {
+            const uint32_t u = (uint32_t)__builtin_ctz(mask);
+            mask &= mask - 1u;
+            __hip_atomic_store(&L.hits[pos++], tag | (at + u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    return true;
+}
+
 // ---- stride 1: one probe per offset (or none: walk every offset) ----------
 //
 // Bit u of round k's 16-bit mask (word k/2, half k%2) marks offset
 // x0 + k*1024 + lane*16 + u as not ruled out.
 template <int R, bool FILTER, int K, bool Q4>
 __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo &ti, const TileRegs<R> &r,
-                                            const uint32_t *bm, uint32_t (&m)[R / 2]) {
+                                            const uint32_t *bm, const uint32_t *bm2, uint32_t (&m)[R / 2]) {
     const uint32_t lane = lane_id();
     const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
     const bool full = ti.x0 >= ti.s.head && ti.x0 + R * kRoundBytes <= ti.s.valid_end;
@@ -834,6 +885,22 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
+            // Second filter, for the few offsets the first one let through
+            // (a lane loops over its own survivors; most lanes have none).
+            if (bm2) {
+                uint32_t left = mask;
+                while (left) {
+                    const uint32_t u = (uint32_t)__builtin_ctz(left);
+                    left &= left - 1u;
+                    const uint32_t a = u >> 2;
+                    const uint32_t lo = a == 0 ? w[0] : a == 1 ? w[1] : a == 2 ? w[2] : w[3];
+                    const uint32_t hi = a == 0 ? w[1] : a == 1 ? w[2] : a == 2 ? w[3] : w[4];
+                    uint32_t g = __builtin_amdgcn_alignbyte(hi, lo, u & 3u);
+                    if (!Q4) g &= qmask;
+                    const uint32_t s2 = glop_slot2(g, GLOP_FILTER2_LOG2);
+                    if (!((bm2[s2 >> 5] >> (s2 & 31u)) & 1u)) mask &= ~(1u << u);
+                }
+            }
         }
         if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
         m[k / 2] |= mask << (16 * (k % 2));
@@ -849,13 +916,16 @@ __device__ __forceinline__ void walk_offsets1(const ScanParams &P, uint64_t t, c
                                               Sink &sink) {
     const uint32_t lane = lane_id();
     uint32_t qhead = 0, qtail = 0;  // wave-uniform ring indices
+    // Half a round at a time, lanes 0-31 and then lanes 32-63, so the queue
+    // holds offsets in ascending order (the emit kernel's rescan writes its
+    // records in queue order) and a half adds at most 512.
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        uint32_t mask = (m[k / 2] >> (16 * (k % 2))) & 0xFFFFu;
+    for (int k = 0; k < 2 * R; ++k) {
+        uint32_t mask = (lane >> 5) == (uint32_t)(k % 2) ? (m[k / 4] >> (16 * ((k / 2) % 2))) & 0xFFFFu : 0u;
         if (__ballot(mask != 0) == 0) continue;
         uint32_t tot;
         uint32_t pos = qtail + wave_prefix_small<5>((uint32_t)__popc(mask), tot);
-        const uint32_t base = (uint32_t)k * kRoundBytes + lane * 16u;
+        const uint32_t base = (uint32_t)(k / 2) * kRoundBytes + lane * 16u;
         while (mask) {
             const uint32_t u = (uint32_t)__builtin_ctz(mask);
             mask &= mask - 1u;
@@ -892,7 +962,7 @@ __device__ __forceinline__ void scan_loaded_tile(const ScanParams &P, uint64_t t
         walk_hits4<R>(P, t, ti, pbits, xb, tabs, queue, sink);
     } else {
         uint32_t m[R / 2];
-        tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, m);
+        tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, nullptr, m);
         walk_offsets1<R>(P, t, ti, m, tabs, queue, sink);
     }
 }
@@ -935,12 +1005,12 @@ __device__ __forceinline__ void reset_item_lds(uint32_t *nm_l, uint64_t *rec_l, 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R, bool BATCH>
 __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
-    constexpr bool kDefer = STRIDE == 4;
+    constexpr bool kDefer = FILTER;  // deferred walks through the workgroup list (every filtered variant)
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t hl_count, item_failed, tile_next;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
-    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes};
+    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -962,6 +1032,15 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.pt_off());
         for (uint32_t k = threadIdx.x; k < P.pt_lds_bytes / 16; k += kBlock) dst[k] = src[k];
         pt = reinterpret_cast<const uint4 *>(lds + Lo.pt_off());
+    }
+    const uint32_t *bm2 = nullptr;
+    if constexpr (STRIDE == 1) {  // the second filter exists for stride 1 only
+        if (P.f2_lds_bytes) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.d.bitmap2);
+            uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.f2_off());
+            for (uint32_t k = threadIdx.x; k < P.f2_lds_bytes / 16; k += kBlock) dst[k] = src[k];
+            bm2 = reinterpret_cast<const uint32_t *>(lds + Lo.f2_off());
+        }
     }
     const WalkTabs tabs{cls, pt};
 
@@ -1004,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         uint32_t c = claim();
         if (c < ntile) {
             cur = tile_info<BATCH, TILE>(P, tb + c);
-            load_tile<R, FILTER, kDefer>(cur, r);
+            load_tile<R, FILTER, STRIDE == 4>(cur, r);
         }
         while (c < ntile) {
             const uint64_t t = tb + c;
@@ -1024,9 +1103,12 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 }
             } else {
                 uint32_t m[R / 2];
-                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, m);
+                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, bm2, m);
                 if (has_next) load_tile<R, FILTER>(nxt, r);
-                walk_offsets1<R>(P, t, cur, m, tabs, queue, sink);
+                // Survivors wait in the workgroup list, so walks run in full
+                // batches of 64 instead of one short batch per tile.
+                if (!kDefer || !list_offsets1<R>(HL, (uint32_t)(t - tb), m))
+                    walk_offsets1<R>(P, t, cur, m, tabs, queue, sink);
             }
             cur = nxt;
             c = cn;
@@ -1035,8 +1117,10 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             // The rest of the list, shared by all waves.
             __syncthreads();
             const uint32_t n = hl_count;
-            for (uint32_t f = wave * 16u; f < n; f += kWaves * 16u)
-                walk_listed<BATCH, TILE>(P, HL, f, min(16u, n - f), tb, tabs, nm_l, rec_l, &item_failed);
+            constexpr uint32_t kPer = STRIDE == 4 ? 16u : 64u;  // entries per walk batch
+            for (uint32_t f = wave * kPer; f < n; f += kWaves * kPer)
+                walk_listed<BATCH, TILE, STRIDE == 4 ? 4 : 1>(P, HL, f, min(kPer, n - f), tb, tabs, nm_l, rec_l,
+                                                              &item_failed);
         }
         __syncthreads();
         // The item's tile results, coalesced, and its total.
@@ -1321,8 +1405,8 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) 
 }
 
 template <int STRIDE, bool BATCH>
-constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes) {
-    return LdsLayout<STRIDE, BATCH>{bm_bytes, pt_bytes}.bytes();
+constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes, uint32_t f2_bytes = 0) {
+    return LdsLayout<STRIDE, BATCH>{bm_bytes, pt_bytes, f2_bytes}.bytes();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R>
@@ -1346,7 +1430,7 @@ struct Kernels {
 
     static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
                           const glop_events_t *ev) {
-        const size_t lds = dyn_lds<STRIDE, false>(P.bm_bytes, P.pt_lds_bytes);
+        const size_t lds = dyn_lds<STRIDE, false>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes);
         const size_t emit_lds = dyn_lds<STRIDE, false>(P.bm_bytes, 0);
         hipError_t e;
         if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
@@ -1362,7 +1446,7 @@ struct Kernels {
 
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
-        const size_t lds = dyn_lds<STRIDE, true>(P.bm_bytes, P.pt_lds_bytes);
+        const size_t lds = dyn_lds<STRIDE, true>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes);
         const size_t emit_lds = dyn_lds<STRIDE, true>(P.bm_bytes, 0);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);

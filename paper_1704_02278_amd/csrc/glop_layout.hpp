@@ -24,6 +24,14 @@
 // also bit glop_slot2(g).  A text position whose q-gram misses any of its bits
 // cannot be where any pattern's t-th q-gram sits.
 //
+// Second filter (stride 1, when the first filter probes one bit or a blocked
+// pair, both from glop_hash1): the same keys in a Bloom filter of
+// 2^GLOP_FILTER2_LOG2 bits, one bit per key at glop_slot2(g), an independent
+// hash.  It is checked only for the offsets the first filter lets through,
+// before they are walked: at stride 1 most walks start at the first filter's
+// false positives, and the walks, not the probes, are most of the time.
+#define GLOP_FILTER2_LOG2 17u
+//
 // Prefix table: when every pattern (as the trie holds it) is at least D bytes
 // long, D = 8 if it can be and 4 otherwise (none below 4), an exact hash table
 // maps each distinct D-byte pattern prefix (little-endian 64-bit key, zero
@@ -95,6 +103,7 @@ struct GlopDevDict {
     const uint8_t *pat_bytes;  // all patterns back to back
     const uint64_t *pat_off;   // first byte of pattern j in pat_bytes
     const uint32_t *pat_len;   // length of pattern j
+    const uint32_t *bitmap2;   // second filter, 2^GLOP_FILTER2_LOG2 bits (null: none)
     // Prefix table (null when some pattern is shorter than 4 bytes).
     const uint32_t *pt;        // 2^pt_lg slots of (key low, key high, entry, 0)
     uint32_t pt_lg, pt_probes;

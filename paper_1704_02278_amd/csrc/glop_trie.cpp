@@ -175,6 +175,16 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
                     c.bitmap[s2 >> 5] |= 1u << (s2 & 31);
                 }
             }
+            // Second filter: stride 1 with a first filter that does not use
+            // glop_hash2 (layout in glop_layout.hpp).
+            c.bitmap2.clear();
+            if (stride == 1 && k != 2) {
+                c.bitmap2.assign((1u << GLOP_FILTER2_LOG2) / 32, 0u);
+                for (uint32_t g : keys) {
+                    const uint32_t s2 = glop_slot2(g, GLOP_FILTER2_LOG2);
+                    c.bitmap2[s2 >> 5] |= 1u << (s2 & 31);
+                }
+            }
         } else {
             if (o.stride > 1 || o.qgram || o.bitmap_log2 || o.probe_bits) {
                 err = "stride/qgram/bitmap/probe options need the q-gram filter";
@@ -185,6 +195,7 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             c.stride = 1;
             c.bitmap_log2 = 12;
             c.bitmap.assign((1u << 12) / 32, 0);
+            c.bitmap2.clear();
         }
         c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
         if (c.tile_kib != 8) {

@@ -22,6 +22,7 @@ struct Compiled {
     uint32_t qgram = 0, qmask = 0, stride = 1, bitmap_log2 = 12, probe_bits = 1, tile_kib = 8;
     uint64_t filter_keys = 0;
     std::vector<uint32_t> bitmap;  // 2^bitmap_log2 bits
+    std::vector<uint32_t> bitmap2; // second filter, 2^GLOP_FILTER2_LOG2 bits, or empty
     // Truncated trie (prefix_len > 0): the trie holds each pattern's first
     // prefix_len bytes; unless `candidates`, the rest is verified per match.
     uint32_t prefix_len = 0, candidates = 0;

@@ -108,6 +108,21 @@ def test_prefix_table_holds_the_distinct_prefixes():
     assert full["prefix_depth"] == 8 and full["prefix_keys"] == info["prefix_keys"]
 
 
+def test_second_filter_only_where_stride_one_walks_follow():
+    """The second filter (checked before stride-1 walks) exists for stride-1
+    dictionaries whose first filter does not use the second hash."""
+    large = synth.gen_patterns(synth.WORKLOADS["large"].patterns, 300, 5)
+    assert min(map(len, large)) < 7
+    info = host_dict(large).info()
+    assert info["stride"] == 1 and info["probe_bits"] == 3 and info["filter2_log2"] == 17
+    assert host_dict(large, probe_bits=1).info()["filter2_log2"] == 17
+    assert host_dict(large, probe_bits=2).info()["filter2_log2"] == 0
+    assert host_dict(large, filter=glop.GLOP_FILTER_NONE).info()["filter2_log2"] == 0
+    medium = synth.gen_patterns(synth.WORKLOADS["medium"].patterns, 300, 5)
+    assert host_dict(medium).info()["stride"] == 4 and host_dict(medium).info()["filter2_log2"] == 0
+    assert host_dict(medium, stride=1).info()["filter2_log2"] == 17
+
+
 def test_automatic_options():
     assert host_dict([b"abcdefg"]).info()["stride"] == 4
     assert host_dict([b"abcdef"]).info()["stride"] == 1

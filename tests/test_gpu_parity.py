@@ -156,6 +156,14 @@ def test_dense_hits_at_stride4_fill_the_workgroup_list():
         d = glop.Dict(pats, **opts)
         assert d.info()["stride"] == 4
         assert_same(gpu_match(d, t), want, f"dense stride4 {opts}")
+    # Stride 1 lists surviving offsets the same way: the list fills after two
+    # tiles, later tiles walk at once, and the emit kernel rescans them all.
+    for opts in (dict(filter=glop.GLOP_FILTER_QGRAM, stride=1),
+                 dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=1)):
+        say("dense-stride1", opts)
+        d = glop.Dict(pats, **opts)
+        assert d.info()["stride"] == 1
+        assert_same(gpu_match(d, t), want, f"dense stride1 {opts}")
 
 
 @pytest.mark.parametrize("n_pats,lo,hi", [(900, 8, 14), (2500, 8, 14), (900, 7, 12), (1500, 7, 12),
