@@ -328,7 +328,8 @@ typedef struct {
     uint32_t prefix_slots;   /* slots of the prefix table (a power of two, or 0) */
     uint32_t prefix_depth;   /* 8 if every pattern is at least 8 bytes, else 4 (or 0) */
     uint32_t filter2_log2;   /* bits (log2) of the second filter checked before
-                                stride-1 walks, or 0 when there is none */
+                                stride-1 walks (three bits per key), or 0 when
+                                there is none */
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 

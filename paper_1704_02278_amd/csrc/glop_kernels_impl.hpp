@@ -897,8 +897,13 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
                     const uint32_t hi = a == 0 ? w[1] : a == 1 ? w[2] : a == 2 ? w[3] : w[4];
                     uint32_t g = __builtin_amdgcn_alignbyte(hi, lo, u & 3u);
                     if (!Q4) g &= qmask;
-                    const uint32_t s2 = glop_slot2(g, GLOP_FILTER2_LOG2);
-                    if (!((bm2[s2 >> 5] >> (s2 & 31u)) & 1u)) mask &= ~(1u << u);
+                    uint32_t h = glop_hash2(g), all = 1u;
+#pragma unroll
+                    for (uint32_t j = 0; j < GLOP_FILTER2_PROBES; ++j, h = glop_f2_next(h)) {
+                        const uint32_t s2 = h >> (32u - GLOP_FILTER2_LOG2);
+                        all &= bm2[s2 >> 5] >> (s2 & 31u);
+                    }
+                    if (!(all & 1u)) mask &= ~(1u << u);
                 }
             }
         }

@@ -181,8 +181,11 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             if (stride == 1 && k != 2) {
                 c.bitmap2.assign((1u << GLOP_FILTER2_LOG2) / 32, 0u);
                 for (uint32_t g : keys) {
-                    const uint32_t s2 = glop_slot2(g, GLOP_FILTER2_LOG2);
-                    c.bitmap2[s2 >> 5] |= 1u << (s2 & 31);
+                    uint32_t h = glop_hash2(g);
+                    for (uint32_t j = 0; j < GLOP_FILTER2_PROBES; ++j, h = glop_f2_next(h)) {
+                        const uint32_t s2 = h >> (32u - GLOP_FILTER2_LOG2);
+                        c.bitmap2[s2 >> 5] |= 1u << (s2 & 31);
+                    }
                 }
             }
         } else {
