@@ -98,7 +98,7 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
 
 using namespace detail;
 
-uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus, kMinTileBytes).bytes; }
+uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus, kMinTileBytes, 15).bytes; }
 
 uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes) {
     return batch_geometry(nchunks, max_total_bytes).bytes;
@@ -133,9 +133,10 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
         return e;
     }
     const uint32_t tile = d.tile_kib * 1024u;
-    const Geometry g = geometry(a.len, a.num_cus, tile);
     ScanParams P = base_params(d, a.counts);
     P.one = make_span(a.text, a.len, d.min_len);
+    const Geometry g = geometry(a.len, a.num_cus, tile, P.one.head);
+    if (g.bytes > a.workspace_bytes) return hipErrorInvalidValue;
     if (a.start_limit && a.start_limit < a.len && P.one.head + a.start_limit < P.one.valid_end)
         P.one.valid_end = P.one.head + a.start_limit;
     P.zero_counts = a.accumulate ? 0u : 1u;

@@ -1374,17 +1374,25 @@ struct Geometry {
 };
 
 // One text: tiles of `tile` bytes, at most kMaxTilesPerItem per workgroup.
-inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile) {
+// Tile coordinates start at the text's first byte rounded down to 16 bytes,
+// `head` bytes before it.  The exact head matters: an aligned 4 GiB text is
+// 2^19 tiles, two rounds of full items on 256 CUs, where one more tile would
+// need a third round.  Every region grows with the number of tiles (the item
+// sums are sized for whole rounds: the item count itself is not monotone, 257
+// tiles make 129 items of 2 and 256 tiles 256 items of 1), so a workspace
+// sized with the smallest tile and head 15 holds every launch of that length.
+inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile, uint64_t head) {
     Geometry g{};
-    g.ntiles = (len + 15 + tile - 1) / tile;  // the text plus up to 15 leading alignment bytes
+    g.ntiles = (head + len + tile - 1) / tile;
     const uint64_t wgs = (uint64_t)(num_cus > 0 ? num_cus : 1);
     g.tiles_per_item = single_tiles_per_item(g.ntiles, wgs);
     g.grid = (uint32_t)(g.ntiles ? (g.ntiles + g.tiles_per_item - 1) / g.tiles_per_item : 0);
+    const uint64_t rounds = g.ntiles ? (g.ntiles + wgs * kMaxTilesPerItem - 1) / (wgs * kMaxTilesPerItem) : 1;
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.ntiles * 8);
     g.off_stage = align256(g.off_nm + g.ntiles * 4);
     g.off_item = align256(g.off_stage + g.ntiles * kStageCap * 8);
-    g.bytes = align256(g.off_item + (uint64_t)g.grid * 8);
+    g.bytes = align256(g.off_item + wgs * rounds * 8);
     return g;
 }
 

@@ -192,6 +192,32 @@ def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
         assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"prefix table {n_pats} {opts}")
 
 
+def test_item_count_flips_with_the_text_alignment():
+    # 2 MiB is 256 tiles of 8 KiB when aligned (256 items of one tile on 256
+    # CUs) but 257 tiles 15 bytes off (129 items of two): the launch's tile
+    # count follows the text's own alignment, and its workspace layout must
+    # still fit the size the library asks for (allocated here to the byte).
+    pats, text, _ = synth.make_workload("medium", n_bytes=(2 << 20) + 64)
+    d = glop.Dict(pats)
+    for n in ((2 << 20) - 15, (2 << 20) - 1, 2 << 20, (2 << 20) + 1, (2 << 20) + 17):
+        sub = text[:n]
+        want = oracle_match(sub, pats)
+        for shift in (0, 1, 15):
+            say("alignment flip", n, shift)
+            t = to_device(sub, shift=shift)
+            nbytes = d.workspace_bytes(n)
+            ws_buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            ws = ws_buf[(-ws_buf.data_ptr()) % 256:][:nbytes]
+            out = torch.empty((want[3] + 64, 2), dtype=torch.int64, device="cuda")
+            counts = torch.empty(len(pats), dtype=torch.int64, device="cuda")
+            total = torch.empty(1, dtype=torch.int64, device="cuda")
+            d.match_into(t, out, counts, total=total, workspace=ws)
+            torch.cuda.synchronize()
+            got = (out[:want[3], 0].cpu().numpy().astype(np.uint64), out[:want[3], 1].cpu().numpy().astype(np.uint64),
+                   counts.cpu().numpy().astype(np.uint64), int(total[0]))
+            assert_same(got, want, f"n {n} shift {shift}")
+
+
 def test_total_written_to_pinned_host_memory():
     # glop_match_ws may take a pinned host word for the total: the emit kernel
     # writes it directly (the server's single-request path relies on this).
