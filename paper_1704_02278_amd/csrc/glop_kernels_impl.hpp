@@ -341,6 +341,31 @@ __device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32
     return hit & 1u;
 }
 
+// The same probe, accumulated: the probe's bit (both bits for K = 2 or 3, one
+// into each accumulator) enters at the top of a1/a2 as their contents move
+// down one place (v_alignbit).  After 16 probes, bit 16 + u of a1 & a2 is
+// probe u's result.  A shift takes its amount modulo 32, so the tested bit
+// needs no mask and no compare: about 10 vector instructions per probe where
+// a 0/1 result costs 12 to 13.
+template <int K, bool Q4>
+__device__ __forceinline__ void probe_acc(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t sh,
+                                          uint32_t &a1, uint32_t &a2) {
+    if (!Q4) g &= qmask;
+    if (K == 3) {
+        const uint32_t h = glop_hash1(g);
+        const uint32_t w = bm[h >> (sh + 5u)];
+        a1 = __builtin_amdgcn_alignbit(w >> ((h >> 8) & 31u), a1, 1u);
+        a2 = __builtin_amdgcn_alignbit(w >> ((h >> 13) & 31u), a2, 1u);
+        return;
+    }
+    const uint32_t s1 = glop_hash1(g) >> sh;
+    a1 = __builtin_amdgcn_alignbit(bm[s1 >> 5] >> (s1 & 31u), a1, 1u);
+    if (K == 2) {
+        const uint32_t s2 = glop_hash2(g) >> sh;
+        a2 = __builtin_amdgcn_alignbit(bm[s2 >> 5] >> (s2 & 31u), a2, 1u);
+    }
+}
+
 // Offsets x .. x+15 that may start a pattern: head <= x+u < valid_end.
 __device__ __forceinline__ uint32_t valid_mask16(const Span &s, uint64_t x) {
     int64_t lo = (int64_t)s.head - (int64_t)x;
@@ -873,18 +898,19 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
             uint32_t nx = __shfl_down(r.v[k].x, 1);
             if (lane == kWave - 1) nx = next0;
             const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
-            mask = 0;
+            uint32_t a1 = 0, a2 = K == 1 ? ~0u : 0u;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
                                            : w[u >> 2];
-                mask |= probe<K, Q4>(bm, g, qmask, sh) << u;
+                probe_acc<K, Q4>(bm, g, qmask, sh, a1, a2);
                 if ((u & 3) == 3) {
                     // Finish these probes here (see tile_hits4).
-                    __asm__ volatile("" : "+v"(mask));
+                    __asm__ volatile("" : "+v"(a1), "+v"(a2));
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
+            mask = (a1 & a2) >> 16;
             // Second filter, for the few offsets the first one let through
             // (a lane loops over its own survivors; most lanes have none).
             if (bm2) {
