@@ -918,18 +918,19 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
                 while (left) {
                     const uint32_t u = (uint32_t)__builtin_ctz(left);
                     left &= left - 1u;
-                    const uint32_t a = u >> 2;
-                    const uint32_t lo = a == 0 ? w[0] : a == 1 ? w[1] : a == 2 ? w[2] : w[3];
-                    const uint32_t hi = a == 0 ? w[1] : a == 1 ? w[2] : a == 2 ? w[3] : w[4];
-                    uint32_t g = __builtin_amdgcn_alignbyte(hi, lo, u & 3u);
+                    // Word pair (w[a], w[a+1]), a = u / 4, picked in two steps.
+                    const bool up = (u & 8u) != 0, odd = (u & 4u) != 0;
+                    const uint32_t p0 = up ? w[2] : w[0], p1 = up ? w[3] : w[1], p2 = up ? w[4] : w[2];
+                    uint32_t g = __builtin_amdgcn_alignbyte(odd ? p2 : p1, odd ? p1 : p0, u & 3u);
                     if (!Q4) g &= qmask;
-                    uint32_t h = glop_hash2(g), all = 1u;
-#pragma unroll
-                    for (uint32_t j = 0; j < GLOP_FILTER2_PROBES; ++j, h = glop_f2_next(h)) {
-                        const uint32_t s2 = h >> (32u - GLOP_FILTER2_LOG2);
-                        all &= bm2[s2 >> 5] >> (s2 & 31u);
-                    }
-                    if (!(all & 1u)) mask &= ~(1u << u);
+                    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h), hk = h + k;
+                    constexpr uint32_t sh2 = 32u - GLOP_FILTER2_LOG2;
+                    const uint32_t all = (bm2[h >> (sh2 + 5u)] >> ((h >> sh2) & 31u)) &
+                                         (bm2[k >> (sh2 + 5u)] >> ((k >> sh2) & 31u)) &
+                                         (bm2[hk >> (sh2 + 5u)] >> ((hk >> sh2) & 31u));
+                    // Bit u of the mask becomes bit 0 of `all` (one v_bfi).
+                    const uint32_t bit = 1u << u;
+                    mask = (mask & ~bit) | ((all << u) & bit);
                 }
             }
         }

@@ -26,16 +26,15 @@
 //
 // Second filter (stride 1, when the first filter probes one bit or a blocked
 // pair, both from glop_hash1): the same keys in a Bloom filter of
-// 2^GLOP_FILTER2_LOG2 bits, GLOP_FILTER2_PROBES bits per key from glop_hash2,
-// an independent hash: the top bits of h = glop_hash2(g), then of
-// glop_f2_next(h), then of glop_f2_next of that.  It is checked only for the
+// 2^GLOP_FILTER2_LOG2 bits, three bits per key from glop_hash2, an independent
+// hash: the top bits of h = glop_hash2(g), of k = glop_f2_mix(h) and of h + k
+// (double hashing).  It is checked only for the
 // offsets the first filter lets through, before they are walked: at stride 1
 // most walks start at the first filter's false positives, and the walks, not
 // the probes, are most of the time.  (On 20,000 4-byte prefixes in log text,
 // one bit per key passed 0.099 % of all offsets, three bits 0.044 %; 0.026 %
 // start a pattern's first four bytes.)
 #define GLOP_FILTER2_LOG2 17u
-#define GLOP_FILTER2_PROBES 3u
 //
 // Prefix table: when every pattern (as the trie holds it) is at least D bytes
 // long, D = 8 if it can be and 4 otherwise (none below 4), an exact hash table
@@ -75,9 +74,9 @@ GLOP_HD uint32_t glop_hash2(uint32_t g) {
 }
 GLOP_HD uint32_t glop_slot1(uint32_t g, uint32_t bitmap_log2) { return glop_hash1(g) >> (32u - bitmap_log2); }
 GLOP_HD uint32_t glop_slot2(uint32_t g, uint32_t bitmap_log2) { return glop_hash2(g) >> (32u - bitmap_log2); }
-// The second filter's further probes: fold the high half down and multiply by
-// an odd constant, so the next slot's top bits depend on every bit of h.
-GLOP_HD uint32_t glop_f2_next(uint32_t h) { return (h ^ (h >> 16)) * 0x7FEB352Du; }
+// The second filter's second hash: one more 24x24-bit multiply-add, of h's
+// upper 24 bits, so its top bits depend on the bits below the first slot too.
+GLOP_HD uint32_t glop_f2_mix(uint32_t h) { return ((h >> 8) & 0xFFFFFFu) * 0xC2B2AEu + h; }
 
 // Blocked variant (probe_bits 3): both bits of a q-gram lie in one 32-bit word,
 // so a probe is one hash and one LDS read.  The word comes from the top

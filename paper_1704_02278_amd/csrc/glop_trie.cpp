@@ -181,9 +181,9 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             if (stride == 1 && k != 2) {
                 c.bitmap2.assign((1u << GLOP_FILTER2_LOG2) / 32, 0u);
                 for (uint32_t g : keys) {
-                    uint32_t h = glop_hash2(g);
-                    for (uint32_t j = 0; j < GLOP_FILTER2_PROBES; ++j, h = glop_f2_next(h)) {
-                        const uint32_t s2 = h >> (32u - GLOP_FILTER2_LOG2);
+                    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h);
+                    for (uint32_t x : {h, k, h + k}) {
+                        const uint32_t s2 = x >> (32u - GLOP_FILTER2_LOG2);
                         c.bitmap2[s2 >> 5] |= 1u << (s2 & 31);
                     }
                 }
