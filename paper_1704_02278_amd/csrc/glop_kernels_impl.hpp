@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
     constexpr bool kDefer = FILTER;  // deferred walks through the workgroup list (every filtered variant)
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t hl_count, item_failed, tile_next;
+    __shared__ uint32_t hl_count, item_failed, tile_next, hl_walked;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
     const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes};
@@ -1088,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                         : (uint64_t)blockIdx.x;
         item_failed = 0;
         tile_next = 0;
-        if (kDefer) hl_count = 0;
+        if (kDefer) hl_count = hl_walked = 0;
     }
     reset_item_lds<kDefer, BATCH>(nm_l, rec_l, HL.hits);
     // A wave takes the item's next tile from an LDS counter whenever it starts
@@ -1138,19 +1138,42 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, bm2, m);
                 if (has_next) load_tile<R, FILTER>(nxt, r);
                 // Survivors wait in the workgroup list, so walks run in full
-                // batches of 64 instead of one short batch per tile.
-                if (!kDefer || !list_offsets1<R>(HL, (uint32_t)(t - tb), m))
+                // batches of 64 instead of one short batch per tile.  Here the
+                // probes keep the vector units busy, so a wave that finds 64
+                // entries nobody has taken walks them now, hidden behind the
+                // other waves' probes, rather than in the item's last phase.
+                if (!kDefer || !list_offsets1<R>(HL, (uint32_t)(t - tb), m)) {
                     walk_offsets1<R>(P, t, cur, m, tabs, queue, sink);
+                } else {
+                    uint32_t first = 0, ok = 0;
+                    if (lane_id() == 0) {
+                        uint32_t w = __hip_atomic_load(&hl_walked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        const uint32_t have = __hip_atomic_load(&hl_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        while (w + 64u <= have) {
+                            const uint32_t prev = atomicCAS(&hl_walked, w, w + 64u);
+                            if (prev == w) {
+                                first = w;
+                                ok = 1;
+                                break;
+                            }
+                            w = prev;
+                        }
+                    }
+                    if (__builtin_amdgcn_readfirstlane(ok))
+                        walk_listed<BATCH, TILE, 1>(P, HL, __builtin_amdgcn_readfirstlane(first), 64u, tb, tabs,
+                                                    nm_l, rec_l, &item_failed);
+                }
             }
             cur = nxt;
             c = cn;
         }
         if (kDefer) {
-            // The rest of the list, shared by all waves.
+            // The rest of the list (stride 1: past what waves took while
+            // streaming), shared by all waves.
             __syncthreads();
-            const uint32_t n = hl_count;
+            const uint32_t n = hl_count, w0 = STRIDE == 1 ? hl_walked : 0u;
             constexpr uint32_t kPer = STRIDE == 4 ? 16u : 64u;  // entries per walk batch
-            for (uint32_t f = wave * kPer; f < n; f += kWaves * kPer)
+            for (uint32_t f = w0 + wave * kPer; f < n; f += kWaves * kPer)
                 walk_listed<BATCH, TILE, STRIDE == 4 ? 4 : 1>(P, HL, f, min(kPer, n - f), tb, tabs, nm_l, rec_l,
                                                               &item_failed);
         }
@@ -1169,7 +1192,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             item_sh = BATCH ? atomicAdd(reinterpret_cast<unsigned long long *>(&P.meta[kMetaTicket]), 1ull) : ~0ull;
             item_failed = 0;
             tile_next = 0;
-            if (kDefer) hl_count = 0;
+            if (kDefer) hl_count = hl_walked = 0;
         }
         reset_item_lds<kDefer, BATCH>(nm_l, rec_l, HL.hits);
     }
