@@ -663,6 +663,22 @@ template <int R, int K, bool Q4>
 __device__ __forceinline__ void tile_hits4(const GlopDevDict &d, const TileRegs<R> &r, const uint32_t *bm,
                                            HitBits<R> &pbits, uint32_t &extra_bit) {
     const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
+    if constexpr (4 * R == 32) {
+        // Exactly 32 probes: accumulated as in tile_masks1, probe i ends at bit i.
+        uint32_t a1 = 0, a2 = K == 1 ? ~0u : 0u;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            probe_acc<K, Q4>(bm, r.v[k].x, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].y, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].z, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].w, qmask, sh, a1, a2);
+            __asm__ volatile("" : "+v"(a1), "+v"(a2));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        pbits = (HitBits<R>)(a1 & a2);
+        extra_bit = probe<K, Q4>(bm, r.extra, qmask, sh);
+        return;
+    }
     HitBits<R> b = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
