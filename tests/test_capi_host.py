@@ -162,6 +162,19 @@ def test_workspace_grows_with_length():
     assert 0 < a < b and b % 256 == 0
 
 
+def test_workspace_never_shrinks_as_the_text_grows():
+    # A workspace sized for one length serves every shorter text (the
+    # host-streamed form sizes one for its largest piece, and a launch lays
+    # out at most what the query sized): across tile and round boundaries the
+    # size never drops as the length grows.
+    d = host_dict([b"abc"])
+    lens = sorted({max(0, k * 8192 + e) for k in (0, 1, 255, 256, 257, 1024, 1025, 4096)
+                   for e in range(-20, 21)})
+    sizes = [d.workspace_bytes(n) for n in lens]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:]))
+    assert all(s % 256 == 0 for s in sizes)
+
+
 def test_size_getters_and_stream_probe_argument_checks():
     d = host_dict([b"abc", b"de", b"fghij"])
     assert glop.glop_num_patterns(d.handle) == 3 == d.num_patterns
