@@ -81,12 +81,16 @@ def flatten_patterns(patterns):
     return blob, offs, lens
 
 
-def match(text, patterns, *, bucketed: bool = True, threads: int | None = None,
+def match(text, patterns, *, bucketed: bool | int = True, threads: int | None = None,
           cap: int | None = None, lib=None):
     """(offsets u64[M'], ids u32[M'], counts u64[n], total M).
 
-    ``cap`` limits how many pairs are returned (None = all, found by a count
-    pass first); the counts and ``total`` are always complete.
+    ``bucketed``: False/0 = every pattern at every offset; True/1 = only the
+    patterns whose first byte is the text byte; 2 = only the 1-byte patterns
+    and those whose first two bytes are the next two text bytes.  All three
+    give the same result.  ``cap`` limits how many pairs are returned (None =
+    all, found by a count pass first); the counts and ``total`` are always
+    complete.
     """
     lib = lib or _load()
     t = _as_u8(text)

@@ -20,10 +20,15 @@
  * pattern ending at the same start; duplicate patterns each report their own
  * index.  Nothing spans two calls: the text is one independent string.
  *
- * Two loops give the same M:
+ * Three loops give the same M:
  *   plain     -- for each i, for each j ascending: memcmp.
  *   bucketed  -- for each i, only the j whose first byte equals T[i], in
  *                ascending j (a pattern with another first byte cannot match).
+ *   bucketed by two bytes -- for each i, the j of length 1 (a side list) and
+ *                the j of length >= 2 whose first two bytes equal T[i], T[i+1]
+ *                (when i + 1 < N), the two ascending lists merged into one
+ *                ascending j; a pattern with other first two bytes cannot
+ *                match, and at the last offset only a 1-byte pattern fits.
  * Work is split over threads by contiguous ranges of i; each range's pairs are
  * produced in order and the ranges are concatenated in order, so the output is
  * identical for any thread count.
@@ -42,7 +47,14 @@ typedef struct {
     uint32_t n_pat;
     const uint32_t *bucket_ids; /* pattern ids grouped by first byte, ascending */
     const uint64_t *bucket_at;  /* 257 entries: bucket b is bucket_ids[at[b] .. at[b+1]) */
-    int bucketed;
+    /* two-byte buckets: patterns of length >= 2 grouped by key p[0] * 256 + p[1],
+       ascending in each bucket (65537 entries in pair_at); patterns of length 1
+       in short_ids, ascending */
+    const uint32_t *pair_ids;
+    const uint64_t *pair_at;
+    const uint32_t *short_ids;
+    uint32_t n_short;
+    int bucketed; /* 0 plain, 1 first byte, 2 first two bytes */
 } problem_t;
 
 typedef struct {
@@ -74,12 +86,34 @@ static inline void record(range_t *r, uint64_t i, uint32_t j) {
     r->found += 1;
 }
 
+/* Two-byte buckets at offset i: the side list of 1-byte patterns and the
+   bucket of T[i], T[i+1] (none at the last offset), merged in ascending j. */
+static void scan_pairs_at(range_t *r, uint64_t i) {
+    const problem_t *pb = r->pb;
+    uint64_t a = 0, a_end = pb->n_short, b = 0, b_end = 0;
+    if (i + 1 < pb->n_text) {
+        uint32_t key = (uint32_t)pb->text[i] * 256u + pb->text[i + 1];
+        b = pb->pair_at[key];
+        b_end = pb->pair_at[key + 1];
+    }
+    while (a < a_end || b < b_end) {
+        uint32_t j;
+        if (b == b_end || (a < a_end && pb->short_ids[a] < pb->pair_ids[b]))
+            j = pb->short_ids[a++];
+        else
+            j = pb->pair_ids[b++];
+        if (occurs_at(pb, i, j)) record(r, i, j);
+    }
+}
+
 static void *scan_range(void *arg) {
     range_t *r = (range_t *)arg;
     const problem_t *pb = r->pb;
     r->found = 0;
     for (uint64_t i = r->lo; i < r->hi; i++) {
-        if (pb->bucketed) {
+        if (pb->bucketed == 2) {
+            scan_pairs_at(r, i);
+        } else if (pb->bucketed) {
             uint8_t first = pb->text[i];
             for (uint64_t k = pb->bucket_at[first]; k < pb->bucket_at[first + 1]; k++) {
                 uint32_t j = pb->bucket_ids[k];
@@ -103,6 +137,7 @@ static void run_ranges(range_t *rs, int threads) {
 
 /*
  * Match n_pat patterns against text[0 .. n_text).
+ *   bucketed:       0 plain, 1 first-byte buckets, 2 two-byte buckets (same M).
  *   out_off/out_id: room for `cap` pairs (may be NULL with cap 0); the first
  *                   min(cap, |M|) pairs of M in order are written.
  *   counts:         n_pat entries, overwritten with C (may be NULL).
@@ -123,10 +158,35 @@ uint64_t oracle_match(const uint8_t *text, uint64_t n_text, const uint8_t *pat_b
     if (threads < 1) threads = 1;
     if ((uint64_t)threads > n_text) threads = (int)n_text;
 
-    problem_t pb = {text, n_text, pat_bytes, pat_off, pat_len, n_pat, NULL, NULL, bucketed};
-    uint32_t *bucket_ids = NULL;
-    uint64_t *bucket_at = NULL;
-    if (bucketed) {
+    problem_t pb = {text, n_text, pat_bytes, pat_off, pat_len, n_pat, NULL, NULL, NULL, NULL, NULL, 0, bucketed};
+    uint32_t *bucket_ids = NULL, *pair_ids = NULL, *short_ids = NULL;
+    uint64_t *bucket_at = NULL, *pair_at = NULL;
+    if (bucketed == 2) {
+        /* counting sort by key: ids stay ascending within each bucket */
+        pair_ids = (uint32_t *)malloc(sizeof(uint32_t) * n_pat);
+        short_ids = (uint32_t *)malloc(sizeof(uint32_t) * n_pat);
+        pair_at = (uint64_t *)calloc(65537, sizeof(uint64_t));
+        uint32_t n_short = 0;
+        for (uint32_t j = 0; j < n_pat; j++) {
+            const uint8_t *p = pat_bytes + pat_off[j];
+            if (pat_len[j] == 1)
+                short_ids[n_short++] = j;
+            else
+                pair_at[(uint32_t)p[0] * 256u + p[1] + 1] += 1;
+        }
+        for (uint32_t k = 0; k < 65536; k++) pair_at[k + 1] += pair_at[k];
+        uint64_t *fill = (uint64_t *)malloc(sizeof(uint64_t) * 65536);
+        memcpy(fill, pair_at, sizeof(uint64_t) * 65536);
+        for (uint32_t j = 0; j < n_pat; j++) {
+            const uint8_t *p = pat_bytes + pat_off[j];
+            if (pat_len[j] >= 2) pair_ids[fill[(uint32_t)p[0] * 256u + p[1]]++] = j;
+        }
+        free(fill);
+        pb.pair_ids = pair_ids;
+        pb.pair_at = pair_at;
+        pb.short_ids = short_ids;
+        pb.n_short = n_short;
+    } else if (bucketed) {
         bucket_ids = (uint32_t *)malloc(sizeof(uint32_t) * n_pat);
         bucket_at = (uint64_t *)calloc(257, sizeof(uint64_t));
         for (uint32_t j = 0; j < n_pat; j++) bucket_at[pat_bytes[pat_off[j]] + 1] += 1;
@@ -170,5 +230,8 @@ uint64_t oracle_match(const uint8_t *text, uint64_t n_text, const uint8_t *pat_b
     free(rs);
     free(bucket_ids);
     free(bucket_at);
+    free(pair_ids);
+    free(pair_at);
+    free(short_ids);
     return total;
 }

@@ -55,8 +55,8 @@ def gpu_match(d: glop.Dict, text_dev: torch.Tensor, max_matches=None):
             counts.cpu().numpy().astype(np.uint64), int(total))
 
 
-def oracle_match(text, patterns, threads=None):
-    off, ids, counts, total = oracle.match(text, patterns, bucketed=True, threads=threads)
+def oracle_match(text, patterns, threads=None, bucketed=1):
+    off, ids, counts, total = oracle.match(text, patterns, bucketed=bucketed, threads=threads)
     return off.astype(np.uint64), ids.astype(np.uint64), counts.astype(np.uint64), int(total)
 
 

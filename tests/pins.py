@@ -5,8 +5,8 @@ returns the names of those that fail.  The regular tests require an empty list;
 the mutation test requires a non-empty one for each planted mistake.
 
 Pins:
-  * hand-derived examples (``golden/hand_examples.txt``), plain and bucketed,
-    with 1 and 3 threads;
+  * hand-derived examples (``golden/hand_examples.txt``), plain and both
+    bucketings (first byte, first two bytes), with 1 and 3 threads;
   * brute force by Python slicing on random tiny inputs over 1-3 letter
     alphabets (forces overlaps, duplicates and prefix chains);
   * single-pattern special case against two library routines: overlapping
@@ -27,7 +27,10 @@ from brute import brute_matches
 from golden_io import load_examples
 
 
-def _run(lib, text: bytes, pats, bucketed: bool, threads: int, cap=None):
+MODES = (0, 1, 2)  # plain, first-byte buckets, two-byte buckets
+
+
+def _run(lib, text: bytes, pats, bucketed: int, threads: int, cap=None):
     off, ids, counts, total = oracle.match(text, pats, bucketed=bucketed, threads=threads, cap=cap, lib=lib)
     return list(zip(off.tolist(), ids.tolist())), counts.tolist(), total
 
@@ -61,7 +64,7 @@ def _single_pattern_refs(text: bytes, p: bytes):
 def pin_failures(lib, n_random: int = 150, seed: int = 1704) -> list[str]:
     failed: list[str] = []
     for ex in load_examples():
-        for bucketed in (False, True):
+        for bucketed in MODES:
             for threads in (1, 3):
                 got, counts, total = _run(lib, ex.text, ex.patterns, bucketed, threads)
                 if got != ex.matches or counts != ex.counts or total != len(ex.matches):
@@ -70,7 +73,7 @@ def pin_failures(lib, n_random: int = 150, seed: int = 1704) -> list[str]:
     for k in range(n_random):
         text, pats = _random_case(rng)
         want, want_counts = brute_matches(text, pats)
-        for bucketed in (False, True):
+        for bucketed in MODES:
             got, counts, total = _run(lib, text, pats, bucketed, 1 + k % 4)
             if got != want or counts != want_counts or total != len(want):
                 failed.append(f"brute:{k}:b{int(bucketed)}")
@@ -79,16 +82,17 @@ def pin_failures(lib, n_random: int = 150, seed: int = 1704) -> list[str]:
         text = bytes(rng.choice(alpha) for _ in range(rng.randint(0, 300)))
         p = bytes(rng.choice(alpha) for _ in range(rng.randint(1, 5)))
         via_re, via_find = _single_pattern_refs(text, p)
-        for bucketed in (False, True):
+        for bucketed in MODES:
             got, counts, total = _run(lib, text, [p], bucketed, 2)
             if not (via_re == via_find == [o for o, _ in got]) or counts != [len(via_re)]:
                 failed.append(f"single:{k}:b{int(bucketed)}")
     text, pats = b"abababab", [b"ab", b"b", b"aba"]
     want, want_counts = brute_matches(text, pats)
     for cap in (0, 1, len(want) - 1):
-        got, counts, total = _run(lib, text, pats, True, 2, cap=cap)
-        if got != want[:cap] or counts != want_counts or total != len(want):
-            failed.append(f"cap:{cap}")
+        for bucketed in (1, 2):
+            got, counts, total = _run(lib, text, pats, bucketed, 2, cap=cap)
+            if got != want[:cap] or counts != want_counts or total != len(want):
+                failed.append(f"cap:{cap}:b{bucketed}")
     return failed
 
 

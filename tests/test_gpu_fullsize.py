@@ -1,12 +1,15 @@
 """Full-size workloads through the launch configuration bench.py times (needs an MI355X).
 
 * medium (1 GiB, 1,000 patterns): every record and count compared with the
-  bucketed oracle over the whole text.
-* large (4 GiB, 20,000 patterns): the full oracle would take minutes of host
-  time, so the whole output is checked by properties that hold at any size
-  (every record is a true occurrence, ascending and unique, counts add up,
-  every planted occurrence is reported) and 128 sampled windows are compared
-  record by record with the oracle run on each window plus its halo.
+  first-byte-bucketed oracle over the whole text.
+* medium dictionary over 2 GiB + 8 KiB of text: one tile more than 256 CUs x
+  1,024 tiles, so the single text is split into two rounds of work items;
+  every record and count against the oracle.
+* large (4 GiB, 20,000 patterns): every record and count compared with the
+  two-byte-bucketed oracle over the whole text (the first-byte bucketing would
+  take most of an hour of host time on this dictionary); the output's
+  properties (true occurrences, strictly ascending, plants present) are checked
+  as well.
 * batched (4,096 independent texts, about 7.7 GiB, medium dictionary) through
   glop_match_batch: every chunk's records, its position and record count, and
   the batch's per-pattern counts, against one oracle run over the chunks laid
@@ -46,24 +49,24 @@ def _properties(text, pats, plants, off, ids, counts, total):
     assert all((o, j) in got for o, j in plants), "a planted occurrence is missing"
 
 
-def test_large_full_size_properties_and_sampled_windows():
+def test_medium_dictionary_two_rounds_bit_exact():
+    n = (2 << 30) + 8192
+    pats, text, plants = synth.make_workload("medium", n_bytes=n)
+    say("fullsize medium dictionary, two rounds of items", text.size)
+    got = gpu_match(glop.Dict(pats), to_device(text))
+    want = oracle_match(text, pats, bucketed=2)
+    assert want[3] >= len(plants)
+    assert_same(got, want, "medium dictionary, 2 GiB + 8 KiB")
+
+
+def test_large_full_size_bit_exact():
     pats, text, plants = synth.make_workload("large")
     say("fullsize large", text.size)
-    off, ids, counts, total = gpu_match(glop.Dict(pats), to_device(text))
-    _properties(text, pats, plants, off, ids, counts, total)
-    maxlen = max(len(p) for p in pats)
-    rng = np.random.default_rng(1704)
-    win = 256 << 10
-    starts = np.sort(rng.integers(0, text.size - win, size=128))
-    starts[0], starts[-1] = 0, text.size - win  # include both ends of the text
-    for s in starts.tolist():
-        lo, hi = s, s + win
-        o_off, o_ids, _, _ = oracle.match(text[lo:min(text.size, hi + maxlen - 1)], pats, bucketed=True)
-        keep = o_off < win
-        w_off = o_off[keep].astype(np.uint64) + np.uint64(lo)
-        w_ids = o_ids[keep].astype(np.uint64)
-        a, b = np.searchsorted(off, lo), np.searchsorted(off, hi)
-        assert np.array_equal(off[a:b], w_off) and np.array_equal(ids[a:b], w_ids), f"window at {lo}"
+    got = gpu_match(glop.Dict(pats), to_device(text))
+    _properties(text, pats, plants, *got)
+    say("fullsize large: oracle (two-byte buckets)")
+    want = oracle_match(text, pats, bucketed=2)
+    assert_same(got, want, "large 4 GiB")
 
 
 def test_batched_full_size_bit_exact():

@@ -52,13 +52,29 @@ def test_oracle_invariants_on_workloads(name, n_bytes):
     assert workload_invariant_failures(text, pats, plants, off, ids, counts, total) == []
 
 
+def _same(a, b):
+    return (np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+            and a[3] == b[3])
+
+
 def test_plain_equals_bucketed_on_workload_slices():
     for name, nb in (("tiny", None), ("medium", 1 << 20), ("large", 96 << 10)):
         pats, text, _ = synth.make_workload(name, n_bytes=nb)
-        a = oracle.match(text, pats, bucketed=False)
-        b = oracle.match(text, pats, bucketed=True)
-        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-        assert np.array_equal(a[2], b[2]) and a[3] == b[3]
+        a = oracle.match(text, pats, bucketed=0)
+        assert _same(a, oracle.match(text, pats, bucketed=1))
+        assert _same(a, oracle.match(text, pats, bucketed=2))
+
+
+@pytest.mark.slow
+def test_two_byte_buckets_equal_first_byte_buckets_on_large_slice():
+    """The two-byte bucketing, which the full-size large-dictionary GPU test
+    compares against, equals the first-byte bucketing (itself equal to the
+    plain loop above) on 256 MiB of the 20,000-pattern workload."""
+    pats, text, plants = synth.make_workload("large", n_bytes=256 << 20)
+    a = oracle.match(text, pats, bucketed=1)
+    b = oracle.match(text, pats, bucketed=2)
+    assert a[3] >= len(plants) > 0
+    assert _same(a, b)
 
 
 # Plausible mistakes, planted in a copy of the oracle source; the pins must
@@ -78,6 +94,18 @@ MUTANTS = {
                              "if (occurs_at(pb, i, j)) { record(r, i, j); break; }\n            }"),
     "reversed-compare": ("memcmp(pb->text + i, pb->pat_bytes + pb->pat_off[j], (size_t)len) == 0",
                          "memcmp(pb->text + i + 1, pb->pat_bytes + pb->pat_off[j], (size_t)len) == 0"),
+    # two-byte buckets
+    "pair-key-swapped": ("uint32_t key = (uint32_t)pb->text[i] * 256u + pb->text[i + 1];",
+                         "uint32_t key = (uint32_t)pb->text[i + 1] * 256u + pb->text[i];"),
+    "pair-drops-short-list": ("uint64_t a = 0, a_end = pb->n_short, b = 0, b_end = 0;",
+                              "uint64_t a = 0, a_end = 0, b = 0, b_end = 0;"),
+    "pair-no-last-offset": ("    if (i + 1 < pb->n_text) {\n        uint32_t key",
+                            "    if (i + 1 >= pb->n_text) return;\n    {\n        uint32_t key"),
+    "pair-short-list-first": ("if (b == b_end || (a < a_end && pb->short_ids[a] < pb->pair_ids[b]))",
+                              "if (a < a_end)"),
+    "pair-bucket-drops-last": ("b_end = pb->pair_at[key + 1];", "b_end = pb->pair_at[key + 1] - (b < pb->pair_at[key + 1]);"),
+    "pair-short-by-length-2": ("if (pat_len[j] == 1)\n                short_ids[n_short++] = j;",
+                               "if (pat_len[j] <= 2)\n                short_ids[n_short++] = j;"),
 }
 
 
