@@ -294,6 +294,32 @@ int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nch
                      uint64_t workspace_bytes, void *stream);
 
 /*
+ * glop_match_batch with a fixed output slice per chunk, so that what one chunk
+ * receives does not depend on the other chunks of the batch (a server batches
+ * independent requests, each with its own output capacity).
+ *
+ *   d_slice_first    device array of nchunks: index in d_out of chunk c's
+ *                    first record.
+ *   d_slice_cap      device array of nchunks: records chunk c may receive.
+ *                    Chunk c's first min(d_chunk_count[c], d_slice_cap[c])
+ *                    occurrences, in (offset, id) order, are written to
+ *                    d_out[d_slice_first[c] ...]; nothing is written past the
+ *                    slice, nor at an index >= max_matches.  Slices should not
+ *                    overlap (overlapping slices receive both chunks' records
+ *                    in no defined order).
+ *   d_chunk_first    as in glop_match_batch: where chunk c's first occurrence
+ *                    would be in the batch's concatenated order (the number
+ *                    of occurrences in chunks before c), not its slice.
+ * Other arguments, the per-pattern counts (always complete) and errors as
+ * glop_match_batch; NULL slice arrays give GLOP_EINVAL.  Allocates nothing.
+ */
+int glop_match_batch_sliced(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks,
+                            uint64_t max_total_bytes, glop_batch_match_t *d_out, uint64_t max_matches,
+                            const uint64_t *d_slice_first, const uint64_t *d_slice_cap, uint64_t *d_chunk_first,
+                            uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                            uint64_t workspace_bytes, void *stream);
+
+/*
  * The failureless-trie walk on the host CPU over the same compiled trie (the
  * CPU counterpart the paper measures in Section 7).  A timing baseline and a
  * check of the trie compiler; glop_match never calls it.

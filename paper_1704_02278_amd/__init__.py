@@ -115,6 +115,8 @@ _SIGNATURES = {
     "glop_batch_workspace_bytes": (_u64, [_vp, ctypes.c_uint32, _u64]),
     "glop_match_batch": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64,
                                         _vp]),
+    "glop_match_batch_sliced": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _vp, _vp, _vp, _vp,
+                                               _vp, _vp, _u64, _vp]),
     "glop_cpu_walk": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, ctypes.c_int]),
     "glop_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(glop_info_t)]),
     "glop_num_patterns": (ctypes.c_uint32, [_vp]),
@@ -302,6 +304,20 @@ class Dict:
                                 out.data_ptr(), cap, chunk_first.data_ptr(), chunk_count.data_ptr(),
                                 counts.data_ptr(), total.data_ptr(), workspace.data_ptr(), int(workspace.numel()),
                                 s), "glop_match_batch")
+
+    def match_batch_sliced_into(self, chunk_table, nchunks, max_total_bytes, out, slice_first, slice_cap,
+                                chunk_first, chunk_count, counts, total, workspace, *, stream=None):
+        """``match_batch_into`` with a fixed output slice per chunk: chunk c's
+        first min(count, slice_cap[c]) records go to out[slice_first[c]:]
+        (slice_first, slice_cap: int64 CUDA tensors [nchunks])."""
+        import torch
+
+        s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+        _check(glop_match_batch_sliced(self._h, chunk_table.data_ptr(), int(nchunks), int(max_total_bytes),
+                                       out.data_ptr(), int(out.shape[0]), slice_first.data_ptr(),
+                                       slice_cap.data_ptr(), chunk_first.data_ptr(), chunk_count.data_ptr(),
+                                       counts.data_ptr(), total.data_ptr(), workspace.data_ptr(),
+                                       int(workspace.numel()), s), "glop_match_batch_sliced")
 
     def match_batch(self, chunks, max_matches=None, stream=None):
         """Match a list of uint8 CUDA tensors as one batch.

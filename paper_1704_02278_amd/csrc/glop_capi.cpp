@@ -708,10 +708,12 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
     return glop::batch_workspace_bytes(nchunks, max_total_bytes);
 }
 
-int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks, uint64_t max_total_bytes,
-                     glop_batch_match_t *d_out, uint64_t max_matches, uint64_t *d_chunk_first,
-                     uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
-                     uint64_t workspace_bytes, void *stream) {
+namespace {
+
+int match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks, uint64_t max_total_bytes,
+                glop_batch_match_t *d_out, uint64_t max_matches, const uint64_t *d_slice_first,
+                const uint64_t *d_slice_cap, uint64_t *d_chunk_first, uint64_t *d_chunk_count, uint64_t *d_counts,
+                uint64_t *d_total, void *d_workspace, uint64_t workspace_bytes, void *stream) {
     if (!h) return fail(GLOP_EINVAL, "NULL handle");
     if (nchunks == 0 || nchunks > (1u << 31)) return fail(GLOP_EINVAL, "nchunks must be 1..2^31");
     if (!d_chunks || !d_chunk_first || !d_chunk_count || !d_total)
@@ -738,9 +740,31 @@ int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nch
     a.total = d_total;
     a.workspace = d_workspace;
     a.num_cus = h->num_cus;
+    a.slice_first = d_slice_first;
+    a.slice_cap = d_slice_cap;
     hipError_t e = glop::launch_batch(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return ok();
+}
+
+}  // namespace
+
+int glop_match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks, uint64_t max_total_bytes,
+                     glop_batch_match_t *d_out, uint64_t max_matches, uint64_t *d_chunk_first,
+                     uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                     uint64_t workspace_bytes, void *stream) {
+    return match_batch(h, d_chunks, nchunks, max_total_bytes, d_out, max_matches, nullptr, nullptr, d_chunk_first,
+                       d_chunk_count, d_counts, d_total, d_workspace, workspace_bytes, stream);
+}
+
+int glop_match_batch_sliced(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks,
+                            uint64_t max_total_bytes, glop_batch_match_t *d_out, uint64_t max_matches,
+                            const uint64_t *d_slice_first, const uint64_t *d_slice_cap, uint64_t *d_chunk_first,
+                            uint64_t *d_chunk_count, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
+                            uint64_t workspace_bytes, void *stream) {
+    if (!d_slice_first || !d_slice_cap) return fail(GLOP_EINVAL, "NULL slice table");
+    return match_batch(h, d_chunks, nchunks, max_total_bytes, d_out, max_matches, d_slice_first, d_slice_cap,
+                       d_chunk_first, d_chunk_count, d_counts, d_total, d_workspace, workspace_bytes, stream);
 }
 
 int glop_cpu_walk(glop_handle_t h, const uint8_t *text, uint64_t len, glop_match_t *out,

@@ -147,7 +147,7 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
     P.tile_nm = reinterpret_cast<uint32_t *>(ws + g.off_nm);
     P.staging = reinterpret_cast<uint64_t *>(ws + g.off_stage);
     P.itemsum = reinterpret_cast<uint64_t *>(ws + g.off_item);
-    const EmitParams E{a.out, a.max_matches, a.total, nullptr, a.base_in, a.offset_add};
+    const EmitParams E{a.out, a.max_matches, a.total, nullptr, a.base_in, a.offset_add, nullptr, nullptr};
     return variant_for(d).one(P, E, g.grid, stream, a.events);
 }
 
@@ -172,7 +172,8 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.tile_start = reinterpret_cast<uint64_t *>(ws + g.off_start);
     P.itemsum = reinterpret_cast<uint64_t *>(ws + g.off_item);
     P.meta = reinterpret_cast<uint64_t *>(ws + g.off_meta);
-    const EmitParams E{reinterpret_cast<glop_match_t *>(a.out), a.max_matches, nullptr, a.chunk_first, nullptr, 0};
+    const EmitParams E{reinterpret_cast<glop_match_t *>(a.out), a.max_matches, nullptr, a.chunk_first, nullptr, 0,
+                       a.slice_first, a.slice_cap};
     return variant_for(d).batch(P, E, a.chunk_count, a.total, a.num_cus, stream);
 }
 

@@ -40,10 +40,13 @@ struct BatchLaunch {
     uint64_t *total;
     void *workspace;
     int num_cus;
+    const uint64_t *slice_first;  // optional per-chunk output slices (both or neither)
+    const uint64_t *slice_cap;
 };
 
 // Device workspace needed for a text of `len` bytes (any alignment).
 uint64_t workspace_bytes(uint64_t len, int num_cus);
+
 
 // Device workspace needed for a batch of nchunks chunks, max_total_bytes in all.
 uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes);

@@ -182,9 +182,38 @@ struct EmitParams {
     uint64_t *chunk_first;   // batch
     const uint64_t *base_in; // single text: device word with the records before this call, or null (0)
     uint64_t offset_add;     // single text: added to every record's offset
+    // Batch, optional: chunk c's j-th record goes to out[slice_first[c] + j]
+    // for j < slice_cap[c] (a fixed slice per chunk) instead of to its
+    // position in the batch's concatenated order.
+    const uint64_t *slice_first;
+    const uint64_t *slice_cap;
 };
 
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+// Write one record: `pos` is its position in the concatenated order, `first`
+// that of its chunk's first record (used with per-chunk slices only).  In a
+// batch, m.reserved holds the chunk (the glop_batch_match_t layout).
+template <bool BATCH>
+__device__ __forceinline__ void put_record(const EmitParams &E, uint64_t pos, uint64_t first, const glop_match_t &m) {
+    if (BATCH && E.slice_first) {
+        const uint64_t j = pos - first;
+        if (j < E.slice_cap[m.reserved]) {
+            const uint64_t q = E.slice_first[m.reserved] + j;
+            if (q < E.max_matches) E.out[q] = m;
+        }
+    } else if (pos < E.max_matches) {
+        E.out[pos] = m;
+    }
+}
+
+// The lane's index, opaque to the optimiser: values derived from it are
+// computed where they are used, not hoisted out of the kernel's loops and held
+// in registers for its whole length (that pushed the stride-1 kernels past
+// their register budget into scratch).
+__device__ __forceinline__ uint32_t lane_id() {
+    uint32_t l = threadIdx.x & (kWave - 1);
+    __asm__ volatile("" : "+v"(l));
+    return l;
+}
 
 // Wave index in the workgroup, known to the compiler as wave-uniform (so the
 // tile indices and addresses derived from it live in scalar registers).
@@ -617,12 +646,15 @@ struct StageSink {
 };
 
 // Sink of the emit kernel's rescan: write the records directly, in order.
+template <bool BATCH>
 struct DirectSink {
     const EmitParams *E;
-    uint64_t base;        // output position of the tile's first record
-    uint64_t cursor = 0;  // records written so far in the tile
+    uint64_t base;         // output position of the tile's first record
+    uint64_t chunk_first;  // output position of its chunk's first record (batch)
+    uint64_t cursor = 0;   // records written so far in the tile
 
-    __device__ __forceinline__ DirectSink(const EmitParams *e, uint64_t b) : E(e), base(b) {}
+    __device__ __forceinline__ DirectSink(const EmitParams *e, uint64_t b, uint64_t f)
+        : E(e), base(b), chunk_first(f) {}
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
@@ -640,7 +672,7 @@ struct DirectSink {
                 const uint32_t id = P.d.outids[first + k];
                 if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
                 const uint64_t pos = base + cursor + excl + j++;
-                if (pos < E->max_matches) E->out[pos] = glop_match_t{i, id, ti.chunk};
+                put_record<BATCH>(*E, pos, chunk_first, glop_match_t{i, id, ti.chunk});
                 atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
             }
         }
@@ -1223,6 +1255,11 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     __shared__ uint32_t n_over, any_over, any_failed;
     __shared__ uint64_t over_tile[kBlock];
     __shared__ uint64_t over_base[kBlock];
+    // Batch with per-chunk slices: output position of each tile of the item
+    // (read for the tiles that start a chunk), and of the first record of the
+    // chunk that began before the item.
+    __shared__ uint64_t tile_first[BATCH ? kMaxBatchTilesPerItem : 1];
+    __shared__ uint64_t carry_first;
     const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
@@ -1263,6 +1300,21 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         // The first block of tile record counts, read beside the sums above.
         const uint64_t rec0 = tb + threadIdx.x < te ? P.tile_rec[tb + threadIdx.x] : 0ull;
         uint64_t base = call_base + block_sum_u64(part, red);  // its barriers publish any_over
+        const bool sliced = BATCH && E.slice_first != nullptr;
+        if (sliced) {
+            // The chunk holding the item's first tile may have begun in an
+            // earlier item i0: its first record follows the records of items
+            // before i0 and of i0's tiles before the chunk's first tile.
+            const uint64_t t0 = P.tile_start[P.tile_chunk[tb]];
+            const uint64_t i0 = t0 / P.tiles_per_item;
+            uint64_t before = 0;
+            if (t0 < tb) {
+                for (uint64_t g = threadIdx.x; g < i0; g += kBlock) before += P.itemsum[g];
+                for (uint64_t t = i0 * P.tiles_per_item + threadIdx.x; t < t0; t += kBlock) before += P.tile_rec[t];
+            }
+            before = block_sum_u64(before, red);
+            if (threadIdx.x == 0) carry_first = before;  // read after the scan's barriers below
+        }
         if (any_over && !staged) {
             stage_tables<FILTER>(P, bm, cls);
             staged = true;
@@ -1275,8 +1327,15 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             const uint64_t rec = c0 == tb ? rec0 : (in ? P.tile_rec[t] : 0ull);
             uint64_t chunk_total;
             const uint64_t tile_base = base + block_excl_scan_u64(rec, scan_sh, chunk_total);
+            if (sliced && in) tile_first[t - tb] = tile_base;  // batch items fit one pass (<= kBlock tiles)
             if (threadIdx.x == 0) n_over = 0;
             __syncthreads();
+            // Output position of the first record of the chunk that tile t lies in.
+            auto chunk_first_pos = [&](uint32_t chunk) -> uint64_t {
+                if (!sliced) return 0;
+                const uint64_t t0 = P.tile_start[chunk];
+                return t0 >= tb ? tile_first[t0 - tb] : carry_first;
+            };
             if (in) {
                 const TileInfo ti = tile_info<BATCH, TILE>(P, t);
                 if (BATCH && t == P.tile_start[ti.chunk]) E.chunk_first[ti.chunk] = tile_base;
@@ -1289,6 +1348,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                     // Staged starts, in ascending offset (slots may be
                     // unordered; offsets are distinct, so the smallest entry
                     // above the last one written is the next).
+                    const uint64_t cf = chunk_first_pos(ti.chunk);
                     uint64_t pos = tile_base;
                     uint64_t prev = 0;
                     for (uint32_t e = 0; e < nm; ++e) {
@@ -1308,7 +1368,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                                 const uint32_t k = (uint32_t)__builtin_ctz(bits);
                                 bits &= bits - 1u;
                                 const uint32_t id = P.d.outids[low + k];
-                                if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
+                                put_record<BATCH>(E, pos, cf, glop_match_t{i, id, ti.chunk});
                                 atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
                                 ++pos;
                             }
@@ -1317,7 +1377,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                             for (uint32_t k = 0; k < cnt; ++k) {
                                 const uint32_t id = P.d.outids[first + k];
                                 if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
-                                if (pos < E.max_matches) E.out[pos] = glop_match_t{i, id, ti.chunk};
+                                put_record<BATCH>(E, pos, cf, glop_match_t{i, id, ti.chunk});
                                 atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
                                 ++pos;
                             }
@@ -1329,10 +1389,20 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             for (uint32_t o = wave; o < n_over; o += kWaves) {
                 const uint64_t ot = over_tile[o];
                 const TileInfo ti = tile_info<BATCH, TILE>(P, ot);
-                TileRegs<R> r;
-                load_tile<R, FILTER>(ti, r);
-                DirectSink sink(&E, over_base[o]);
-                scan_loaded_tile<STRIDE, FILTER, K, Q4, R>(P, ot, ti, r, bm, tabs, queue, sink);
+                DirectSink<BATCH> sink(&E, over_base[o], chunk_first_pos(ti.chunk));
+                // Two rounds at a time, in order, through one sink: a rare
+                // path that keeps a quarter of the tile in registers (the whole
+                // tile would push the kernel past its register budget).
+                constexpr int kSub = 2;
+                for (int s = 0; s < R / kSub; ++s) {
+                    TileInfo sub = ti;
+                    sub.x0 = ti.x0 + (uint64_t)s * kSub * kRoundBytes;
+                    sub.interior =
+                        (sub.x0 >= sub.s.head && sub.x0 + kSub * kRoundBytes + 4 <= sub.s.span_end) ? 1u : 0u;
+                    TileRegs<kSub> r;
+                    load_tile<kSub, FILTER>(sub, r);
+                    scan_loaded_tile<STRIDE, FILTER, K, Q4, kSub>(P, ot, sub, r, bm, tabs, queue, sink);
+                }
             }
             __syncthreads();
             base += chunk_total;

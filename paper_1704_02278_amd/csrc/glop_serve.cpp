@@ -65,6 +65,7 @@ struct Inflight {
     std::shared_ptr<Block> block;
     glop_match_t *out = nullptr;
     uint64_t cap = 0;
+    std::vector<uint64_t> slice;  // batch: first record index of each request's output slice
     int64_t launch_ns = 0;
     hipEvent_t done = nullptr;
     int slot = -1;
@@ -75,7 +76,9 @@ struct Inflight {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    glop_chunk_t *h_table = nullptr;  // pinned, max_batch_requests entries
+    // pinned, room for max_batch_requests entries: a batch of n requests
+    // uses chunk table[n] | slice_first[n] | slice_cap[n], copied in one piece
+    glop_chunk_t *h_table = nullptr;
     uint64_t *h_res = nullptr;        // pinned: first[n] | count[n] | total, copied back in one piece
     bool busy = false;
 };
@@ -118,8 +121,10 @@ struct glop_server {
 
     // Budget for a batch's own memory (tables, workspace) of n requests, `bytes` in all.
     uint64_t batch_own(uint32_t dict, uint32_t n, uint64_t bytes) const {
-        return align256((uint64_t)n * 16) + 2 * align256((uint64_t)n * 8) + align256((uint64_t)npat[dict] * 8) + 256 +
-               align256(glop_batch_workspace_bytes(dicts[dict], n, bytes)) + 256;
+        // Chunk table and slices, per-request results and total, counts, workspace (the layout of
+        // launch_batched_locked's device block before its records).
+        return align256((uint64_t)n * 32) + align256((2ull * n + 1) * 8) + align256((uint64_t)npat[dict] * 8) +
+               align256(glop_batch_workspace_bytes(dicts[dict], n, bytes));
     }
 
     uint64_t plain_own(uint32_t dict, uint64_t len) const {
@@ -155,18 +160,21 @@ struct glop_server {
                 c.request_id = r.id;
                 c.tag = r.tag;
                 c.dict = r.dict;
+                // Each request owns a slice of out_capacity(len) records,
+                // alone or in a batch, so what it receives does not depend on
+                // the requests it shares a launch with.
                 uint64_t first = 0, count = 0;
                 if (f.single) {
                     count = sl.h_res[0];
                 } else {
-                    first = sl.h_res[i];
+                    first = f.slice[i];
                     count = sl.h_res[nreq + i];
                     if (sl.h_res[2 * nreq] == ~0ull) set_error(GLOP_EINTERNAL, "batch workspace overflow");
                 }
                 c.matches = count;
-                c.records = first >= f.cap ? 0 : std::min<uint64_t>(count, f.cap - first);
+                c.records = std::min<uint64_t>(count, out_capacity(r.len));
                 c.truncated = c.records < count ? 1u : 0u;
-                c.d_records = f.out + std::min<uint64_t>(first, f.cap);
+                c.d_records = f.out + first;
                 c.arrival_ns = r.arrival_ns;
                 c.launch_ns = f.launch_ns;
                 c.done_ns = t;
@@ -236,8 +244,9 @@ struct glop_server {
         Slot &sl = slots[si];
         if (n == 1) return launch_single_locked(si, q.front(), dict, &q);
         const uint64_t own = batch_own(dict, n, bytes);
-        // Device block: table | first[n] count[n] total (one copy back) | counts | workspace | records.
-        const uint64_t o_table = 0, o_res = align256((uint64_t)n * 16);
+        // Device block: table, slices | first[n] count[n] total (one copy back) | counts | workspace |
+        // records (one slice per request).
+        const uint64_t o_table = 0, o_res = align256((uint64_t)n * 32);
         const uint64_t o_counts = o_res + align256((2ull * n + 1) * 8);
         const uint64_t o_ws = o_counts + align256((uint64_t)npat[dict] * 8);
         const uint64_t ws_bytes = glop_batch_workspace_bytes(dicts[dict], n, bytes);
@@ -250,10 +259,15 @@ struct glop_server {
         Inflight f;
         f.reqs.assign(q.begin(), q.begin() + n);
         q.erase(q.begin(), q.begin() + n);
-        for (uint32_t i = 0; i < n; ++i) {
+        uint64_t *h_slice_first = reinterpret_cast<uint64_t *>(sl.h_table + n), *h_slice_cap = h_slice_first + n;
+        f.slice.resize(n);
+        for (uint32_t i = 0, at = 0; i < n; ++i) {
             f.reqs[i].reserved = request_need(f.reqs[i].len);
             sl.h_table[i].text = f.reqs[i].len ? f.reqs[i].text : nullptr;
             sl.h_table[i].len = f.reqs[i].len;
+            h_slice_first[i] = f.slice[i] = at;
+            h_slice_cap[i] = out_capacity(f.reqs[i].len);
+            at += h_slice_cap[i];
         }
         reserved += need + own;
         f.block = blk;
@@ -262,14 +276,15 @@ struct glop_server {
         f.slot = si;
         f.done = sl.done;
         f.launch_ns = now_ns();
-        hipError_t e = hipMemcpyAsync(b + o_table, sl.h_table, (uint64_t)n * sizeof(glop_chunk_t),
-                                      hipMemcpyHostToDevice, sl.stream);
+        hipError_t e = hipMemcpyAsync(b + o_table, sl.h_table, (uint64_t)n * 32, hipMemcpyHostToDevice, sl.stream);
         int rc = e == hipSuccess ? GLOP_OK : GLOP_EHIP;
         if (rc == GLOP_OK)
-            rc = glop_match_batch(dicts[dict], reinterpret_cast<const glop_chunk_t *>(b + o_table), n, bytes,
-                                  reinterpret_cast<glop_batch_match_t *>(f.out), cap, res, res + n,
-                                  reinterpret_cast<uint64_t *>(b + o_counts), res + 2 * n, b + o_ws, ws_bytes,
-                                  sl.stream);
+            rc = glop_match_batch_sliced(dicts[dict], reinterpret_cast<const glop_chunk_t *>(b + o_table), n, bytes,
+                                         reinterpret_cast<glop_batch_match_t *>(f.out), cap,
+                                         reinterpret_cast<const uint64_t *>(b + o_table + (uint64_t)n * 16),
+                                         reinterpret_cast<const uint64_t *>(b + o_table + (uint64_t)n * 24), res,
+                                         res + n, reinterpret_cast<uint64_t *>(b + o_counts), res + 2 * n, b + o_ws,
+                                         ws_bytes, sl.stream);
         if (rc == GLOP_OK &&
             ((e = hipMemcpyAsync(sl.h_res, res, (2ull * n + 1) * 8, hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
              (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess))
@@ -433,7 +448,7 @@ glop_server_t glop_server_create(const glop_server_opts *opts) {
         if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
             return create_fail(s, GLOP_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
         const uint64_t n = o.max_batch_requests;
-        if (hipHostMalloc((void **)&sl.h_table, n * sizeof(glop_chunk_t), hipHostMallocDefault) != hipSuccess ||
+        if (hipHostMalloc((void **)&sl.h_table, n * 32, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_res, (2 * n + 1) * 8, hipHostMallocDefault) != hipSuccess)
             return create_fail(s, GLOP_ENOMEM, "pinned host allocation failed");
     }

@@ -1,4 +1,5 @@
-"""Check the gfx950 assembly of the kernels for barriers in divergent loops.
+"""Check the gfx950 assembly of the kernels for barriers in divergent loops
+and for scratch use.
 
 A workgroup barrier (s_barrier) is counted per wave: a wave arrives when its
 active lanes reach it.  If the compiler gives a loop that holds a barrier a
@@ -111,14 +112,41 @@ def check_function(body):
     return sorted(problems)
 
 
+_KD = re.compile(r"^\s*\.amdhsa_kernel\s+(\S+)")
+_PRIVATE = re.compile(r"^\s*\.amdhsa_private_segment_fixed_size\s+(\d+)")
+
+
+def scratch_sizes(lines):
+    """Per-lane scratch bytes of every kernel, from its kernel descriptor."""
+    out, name = {}, None
+    for line in lines:
+        m = _KD.match(line)
+        if m:
+            name = m.group(1)
+            continue
+        m = _PRIVATE.match(line)
+        if m and name is not None:
+            out[name] = int(m.group(1))
+            name = None
+    return out
+
+
 def check_file(path):
-    """Problems in every kernel of one assembly file: {kernel: [problems]}."""
+    """Problems in every kernel of one assembly file: {kernel: [problems]}.
+
+    Besides barriers in divergent loops, a kernel that uses scratch memory (a
+    register spill) is a problem: the kernels are written to fit their
+    register budget, and a spill slot is memory no test of the result covers.
+    """
     lines = Path(path).read_text().splitlines()
     out = {}
     for name, body in _functions(lines):
         p = check_function(body)
         if p:
             out[name] = p
+    for name, size in scratch_sizes(lines).items():
+        if size > 0:
+            out.setdefault(name, []).append(f"uses {size} bytes of scratch per lane (register spill)")
     return out
 
 

@@ -341,6 +341,17 @@ def sha256_bytes(buf) -> str:
     return hashlib.sha256(memoryview(buf)).hexdigest()
 
 
+def sha256_patterns(patterns) -> str:
+    """SHA-256 of a pattern set in id order: each pattern as its length (4-byte
+    little-endian) followed by its bytes, so no two different lists collide by
+    concatenation."""
+    h = hashlib.sha256()
+    for p in patterns:
+        h.update(len(p).to_bytes(4, "little"))
+        h.update(bytes(p))
+    return h.hexdigest()
+
+
 def make_workload(name: str, seed: int = BASE_SEED, n_bytes: int | None = None,
                   threads: int | None = None):
     """(patterns, text, plants) for a named workload; ``n_bytes`` may shrink the text."""

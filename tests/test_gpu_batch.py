@@ -173,3 +173,65 @@ def test_batch_graph_replays_with_a_new_chunk_table():
     _check_batch(d, pats, pieces_b, chunks_b,
                  (out[:eager_b[4], 0], out[:eager_b[4], 1] & 0xFFFFFFFF, out[:eager_b[4], 1] >> 32,
                   first, count, counts, eager_b[4]))
+
+
+SENTINEL = -0x0123456789ABCDEF
+
+
+def test_batch_sliced_outputs_each_chunk_into_its_own_slice():
+    """glop_match_batch_sliced: chunk c's first min(count, cap_c) records land in
+    its own slice and nothing else is written, whatever the other chunks hold:
+    dense chunks (the emit kernel's rescan path) beside sparse ones, chunks that
+    span several work items (their first record lies in an earlier item), caps
+    of 0, 1, below, at and above the chunk's count."""
+    rng = np.random.default_rng(11)
+    pats, text, _ = synth.make_workload("medium", n_bytes=8 << 20)
+    pats = pats + [b"abcdefgh", b"bcdefgha"]
+    dense = (b"abcdefgh" * 80_000)
+    pieces = [dense[:300_000], text[:200_000].tobytes(), dense[3:900_003], text[300_000:301_000].tobytes(), b"",
+              text[400_000:1_400_000].tobytes(), dense[:20_000], text[2_000_000:2_000_007].tobytes()]
+    pieces += _mixed_pieces(text, rng, 40)
+    buf, chunks = _chunks_in_one_buffer(pieces)
+    want = [oracle_match(p, pats, threads=4) for p in pieces]
+    caps = []
+    for k, (_, _, _, w_total) in enumerate(want):
+        choice = k % 5
+        caps.append([0, 1, max(0, w_total - 3), w_total, w_total + 5][choice])
+    gap = 3
+    slice_first = np.zeros(len(pieces), dtype=np.int64)
+    slice_first[1:] = np.cumsum(np.array(caps, dtype=np.int64) + gap)[:-1]
+    n_out = int(slice_first[-1] + caps[-1] + gap)
+    dev = buf.device
+    table = torch.tensor([[c.data_ptr() if c.numel() else 0, c.numel()] for c in chunks], dtype=torch.int64).to(dev)
+    total_bytes = sum(len(p) for p in pieces)
+    for opts in (dict(), dict(filter=glop.GLOP_FILTER_QGRAM, stride=1), dict(prefix_len=glop.GLOP_PREFIX_FULL)):
+        say("batch-sliced", len(pieces), opts)
+        d = glop.Dict(pats, **opts)
+        ws = torch.empty(d.batch_workspace_bytes(len(pieces), total_bytes) + 256, dtype=torch.uint8, device=dev)
+        ws = ws[(-ws.data_ptr()) % 256:]
+        out = torch.full((n_out, 2), SENTINEL, dtype=torch.int64, device=dev)
+        first = torch.empty(len(pieces), dtype=torch.int64, device=dev)
+        count = torch.empty(len(pieces), dtype=torch.int64, device=dev)
+        counts = torch.empty(len(pats), dtype=torch.int64, device=dev)
+        total = torch.zeros(1, dtype=torch.int64, device=dev)
+        sf = torch.from_numpy(slice_first).to(dev)
+        sc = torch.tensor(caps, dtype=torch.int64, device=dev)
+        d.match_batch_sliced_into(table, len(pieces), total_bytes, out, sf, sc, first, count, counts, total, ws)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        written = np.zeros(n_out, dtype=bool)
+        pos = 0
+        want_counts = np.zeros(len(pats), dtype=np.uint64)
+        for c, (w_off, w_ids, w_counts, w_total) in enumerate(want):
+            assert int(count[c]) == w_total and int(first[c]) == pos, f"chunk {c}: count/first"
+            k = min(w_total, caps[c])
+            seg = o[slice_first[c]:slice_first[c] + k]
+            assert np.array_equal(seg[:, 0].astype(np.uint64), w_off[:k]), f"chunk {c}: offsets"
+            assert np.array_equal((seg[:, 1] & 0xFFFFFFFF).astype(np.uint64), w_ids[:k]), f"chunk {c}: ids"
+            assert np.all(seg[:, 1] >> 32 == c), f"chunk {c}: chunk field"
+            written[slice_first[c]:slice_first[c] + k] = True
+            pos += w_total
+            want_counts += w_counts
+        assert np.all(o[~written] == SENTINEL), "a record was written outside its chunk's slice"
+        assert int(total.item()) == pos
+        assert np.array_equal(counts.cpu().numpy().astype(np.uint64), want_counts)

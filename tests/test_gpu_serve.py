@@ -139,3 +139,45 @@ def _device_records(ptr, n):
     rc = hip.hipMemcpy(out.data_ptr(), ptr, n * 16, 3)  # device to device
     assert rc == 0
     return out
+
+
+def test_dense_request_in_a_batch_gets_what_it_gets_alone():
+    """A request with more occurrences than its output capacity (max(64,
+    len / 256) records) shares a batch with sparse requests: it is cut at its
+    own capacity and flagged truncated, as when matched alone, and the requests
+    after it keep all their records."""
+    pats = [b"abab", b"babab", b"xq7#z"]
+    rng = np.random.default_rng(3)
+    sparse = [bytes(rng.integers(0x20, 0x7F, size=n, dtype=np.uint8)) + b"xq7#z" for n in (5000, 70_000, 300)]
+    texts = [b"ab" * 40_000] + sparse + [b"abab" * 3000, sparse[1]]
+    # The first request (256 MiB, no occurrence) holds the only stream slot
+    # while the others, all due at once, queue behind it and go out together.
+    dev = [torch.full((256 << 20,), ord("k"), dtype=torch.uint8, device="cuda")]
+    dev += [torch.frombuffer(bytearray(t), dtype=torch.uint8).cuda() for t in texts]
+    h = glop.Dict(pats)
+    alone = []
+    for t in dev:
+        cap = max(64, t.numel() // 256)
+        o, i, _, total = h.match(t)
+        alone.append((o[:cap].cpu().numpy(), (i[:cap] & 0xFFFFFFFF).cpu().numpy(), total, cap))
+    assert alone[1][2] > alone[1][3] and alone[5][2] > alone[5][3], "the dense requests must exceed their capacity"
+    caps = np.array([a[3] for a in alone], dtype=np.uint64)
+    base = np.zeros(len(dev), dtype=np.uint64)
+    base[1:] = np.cumsum(caps)[:-1]
+    copy_out = torch.full((int(caps.sum()), 2), -1, dtype=torch.int64, device="cuda")
+    srv = glop.Server([h], max_inflight=1)
+    try:
+        say("serve dense request in a batch")
+        lat, matches, trunc, batch, _ = srv.run_trace(np.zeros(len(dev)), [t.data_ptr() for t in dev],
+                                                      [t.numel() for t in dev], np.zeros(len(dev)), copy_out, base,
+                                                      caps)
+    finally:
+        srv.close()
+    assert batch[1:].max() > 1, "the queued requests did not share a batch"
+    rec = copy_out.cpu().numpy()
+    for k, (w_off, w_ids, w_total, cap) in enumerate(alone):
+        assert matches[k] == w_total, f"request {k}: matches"
+        assert bool(trunc[k]) == (w_total > cap), f"request {k}: truncated flag"
+        got = rec[int(base[k]):int(base[k]) + min(w_total, cap)]
+        assert np.array_equal(got[:, 0], w_off) and np.array_equal(got[:, 1] & 0xFFFFFFFF, w_ids), \
+            f"request {k}: records differ from the request matched alone"

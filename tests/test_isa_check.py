@@ -90,3 +90,24 @@ def test_accepts_uniform_exit_with_divergent_inner_loop(tmp_path):
 
 def test_divergent_loop_without_barrier_is_fine(tmp_path):
     assert _check(GOOD.replace("\ts_barrier\n", ""), tmp_path) == {}
+
+
+def _descriptor(name, scratch):
+    return f"""\
+	.amdhsa_kernel {name}
+		.amdhsa_group_segment_fixed_size 160
+		.amdhsa_private_segment_fixed_size {scratch}
+		.amdhsa_kernarg_size 304
+	.end_amdhsa_kernel
+"""
+
+
+def test_flags_a_kernel_that_spills_to_scratch(tmp_path):
+    got = _check(GOOD + _descriptor("kern", 0) + _descriptor("spilly", 64), tmp_path)
+    assert got == {"spilly": ["uses 64 bytes of scratch per lane (register spill)"]}
+
+
+def test_scratch_sizes_read_from_every_descriptor(tmp_path):
+    f = tmp_path / "k.s"
+    f.write_text(_descriptor("a", 0) + _descriptor("b", 8) + _descriptor("c", 0))
+    assert isa_check.scratch_sizes(f.read_text().splitlines()) == {"a": 0, "b": 8, "c": 0}

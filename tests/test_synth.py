@@ -95,3 +95,9 @@ def test_chunked_workload_shape():
         for o, j in plants[k]:
             assert chunk[o:o + len(pats[j])].tobytes() == pats[j]
         assert chunk[-1] == 0x0A  # every chunk ends a line
+
+
+def test_pattern_set_hash_separates_boundaries():
+    assert synth.sha256_patterns([b"ab", b"c"]) != synth.sha256_patterns([b"a", b"bc"])
+    assert synth.sha256_patterns([b"ab", b"c"]) == synth.sha256_patterns([b"ab", b"c"])
+    assert synth.sha256_patterns([]) == synth.sha256_bytes(b"")
