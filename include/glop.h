@@ -104,11 +104,38 @@ typedef struct glop_dict *glop_handle_t;
  *               i.e. every (offset, id) whose first min(prefix_len, length)
  *               bytes match (the truncated matching of Sections 2 and 5, which
  *               can report false positives).  This changes the result.
+ *   layout      how the transition table is stored on the device (Section 5
+ *               ties the table's footprint to the cache hit rate; Section 8
+ *               names a smaller footprint for larger state machines):
+ *               GLOP_LAYOUT_DENSE = one row of num_classes next states per
+ *                    state (one lookup per step);
+ *               GLOP_LAYOUT_HYBRID = dense rows for the states of depth <= 2
+ *                    (where walks branch), and below them one 8-byte node per
+ *                    state naming its children, which breadth-first numbering
+ *                    keeps contiguous (a state with one child, the common case
+ *                    deep in a trie, is one lookup; with more, one more read of
+ *                    the children's edge bytes): a few MB where the dense table
+ *                    needs a hundred;
+ *               GLOP_LAYOUT_AUTO (0) = hybrid when the dense table would exceed
+ *                    32 MiB, else dense.
+ *   placement   where the walks read the dense rows from:
+ *               GLOP_PLACE_GLOBAL = device memory (through L2 / MALL);
+ *               GLOP_PLACE_LDS = a copy staged in each workgroup's LDS (the
+ *                    role Section 6 gives texture memory); GLOP_EINVAL at build
+ *                    if it does not fit beside the scan kernel's other tables;
+ *               GLOP_PLACE_AUTO (0) = LDS when the dense rows take at most
+ *                    32 KiB and fit, else global.
  */
 #define GLOP_PREFIX_FULL 0xFFFFFFFFu
 #define GLOP_FILTER_AUTO 0
 #define GLOP_FILTER_NONE 1
 #define GLOP_FILTER_QGRAM 2
+#define GLOP_LAYOUT_AUTO 0
+#define GLOP_LAYOUT_DENSE 1
+#define GLOP_LAYOUT_HYBRID 2
+#define GLOP_PLACE_AUTO 0
+#define GLOP_PLACE_GLOBAL 1
+#define GLOP_PLACE_LDS 2
 typedef struct {
     int32_t filter;
     uint32_t stride;
@@ -118,6 +145,8 @@ typedef struct {
     uint32_t tile_kib;
     uint32_t prefix_len;
     uint32_t candidates;
+    uint32_t layout;
+    uint32_t placement;
 } glop_build_opts;
 
 /*
@@ -340,7 +369,8 @@ typedef struct {
     uint32_t min_len, max_len;
     uint32_t num_classes;    /* byte classes incl. class 0 ("no pattern uses this byte") */
     uint64_t num_states;     /* trie states incl. the root */
-    uint64_t table_bytes;    /* transition table size on the device */
+    uint64_t table_bytes;    /* transition table size on the device (dense rows, plus
+                                the nodes and edge bytes of the hybrid layout) */
     uint64_t outlist_ids;    /* total entries of the per-state output lists */
     int32_t filter;          /* GLOP_FILTER_NONE or GLOP_FILTER_QGRAM as chosen */
     uint32_t stride, qgram, bitmap_log2, probe_bits, tile_kib;
@@ -356,6 +386,10 @@ typedef struct {
     uint32_t filter2_log2;   /* bits (log2) of the second filter checked before
                                 stride-1 walks (three bits per key), or 0 when
                                 there is none */
+    uint32_t layout;         /* GLOP_LAYOUT_DENSE or GLOP_LAYOUT_HYBRID as chosen */
+    uint32_t placement;      /* GLOP_PLACE_GLOBAL or GLOP_PLACE_LDS as chosen
+                                (GLOP_PLACE_GLOBAL for a host-only handle) */
+    uint64_t dense_states;   /* states stored as dense rows (all of them when dense) */
 } glop_info_t;
 int glop_get_info(glop_handle_t h, glop_info_t *out);
 

@@ -38,6 +38,12 @@ GLOP_PREFIX_FULL = 0xFFFFFFFF
 GLOP_FILTER_AUTO = 0
 GLOP_FILTER_NONE = 1
 GLOP_FILTER_QGRAM = 2
+GLOP_LAYOUT_AUTO = 0
+GLOP_LAYOUT_DENSE = 1
+GLOP_LAYOUT_HYBRID = 2
+GLOP_PLACE_AUTO = 0
+GLOP_PLACE_GLOBAL = 1
+GLOP_PLACE_LDS = 2
 GLOP_MAX_PATTERN_LEN = 65535
 MATCH_RECORD_BYTES = 16
 
@@ -49,7 +55,8 @@ class glop_match_t(ctypes.Structure):
 class glop_build_opts(ctypes.Structure):
     _fields_ = [("filter", ctypes.c_int32), ("stride", ctypes.c_uint32), ("qgram", ctypes.c_uint32),
                 ("bitmap_log2", ctypes.c_uint32), ("probe_bits", ctypes.c_uint32), ("tile_kib", ctypes.c_uint32),
-                ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32)]
+                ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32), ("layout", ctypes.c_uint32),
+                ("placement", ctypes.c_uint32)]
 
 
 class glop_chunk_t(ctypes.Structure):
@@ -92,7 +99,8 @@ class glop_info_t(ctypes.Structure):
         ("prefix_len", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
         ("device_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
         ("prefix_keys", ctypes.c_uint32), ("prefix_slots", ctypes.c_uint32), ("prefix_depth", ctypes.c_uint32),
-        ("filter2_log2", ctypes.c_uint32),
+        ("filter2_log2", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("placement", ctypes.c_uint32),
+        ("dense_states", ctypes.c_uint64),
     ]
 
 
@@ -169,18 +177,20 @@ def _pattern_arrays(patterns):
 
 
 def _opts(filter=GLOP_FILTER_AUTO, stride=0, qgram=0, bitmap_log2=0, probe_bits=0, tile_kib=0, prefix_len=0,
-          candidates=False):
+          candidates=False, layout=GLOP_LAYOUT_AUTO, placement=GLOP_PLACE_AUTO):
     return glop_build_opts(int(filter), int(stride), int(qgram), int(bitmap_log2), int(probe_bits), int(tile_kib),
-                           int(prefix_len), 1 if candidates else 0)
+                           int(prefix_len), 1 if candidates else 0, int(layout), int(placement))
 
 
 class Dict:
     """A compiled dictionary on the current device (or host-only with ``device=False``)."""
 
     def __init__(self, patterns, *, device: bool = True, filter=GLOP_FILTER_AUTO, stride=0, qgram=0,
-                 bitmap_log2=0, probe_bits=0, tile_kib=0, prefix_len=0, candidates=False):
+                 bitmap_log2=0, probe_bits=0, tile_kib=0, prefix_len=0, candidates=False, layout=GLOP_LAYOUT_AUTO,
+                 placement=GLOP_PLACE_AUTO):
         keep, ptrs, lens, n = _pattern_arrays(patterns)
-        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits, tile_kib, prefix_len, candidates)
+        opts = _opts(filter, stride, qgram, bitmap_log2, probe_bits, tile_kib, prefix_len, candidates, layout,
+                     placement)
         fn = glop_build_ex if device else glop_compile
         h = fn(ctypes.cast(ptrs, _u8pp), lens, n, ctypes.byref(opts))
         if not h:
@@ -415,7 +425,8 @@ def autotune(patterns, sample, stream=None) -> dict:
     del keep
     o = r.opts
     return {"opts": {"filter": o.filter, "stride": o.stride, "qgram": o.qgram, "bitmap_log2": o.bitmap_log2,
-                     "probe_bits": o.probe_bits, "tile_kib": o.tile_kib, "prefix_len": o.prefix_len},
+                     "probe_bits": o.probe_bits, "tile_kib": o.tile_kib, "prefix_len": o.prefix_len,
+                     "layout": o.layout, "placement": o.placement},
             "ms": float(r.ms), "auto_ms": float(r.auto_ms), "evaluated": int(r.evaluated),
             "from_cache": bool(r.from_cache)}
 

@@ -74,10 +74,24 @@ int upload(glop_dict *h) {
         }
     }
     const glop::Compiled &c = h->c;
+    // Where the walks read the dense rows: LDS when asked for (or, automatic,
+    // when they take at most kAutoLdsTable bytes) and they fit beside the scan
+    // kernel's other LDS tables for this dictionary.
+    const uint64_t dense_bytes = (uint64_t)c.n_dense * c.num_classes * 4;
+    const bool fits = dense_bytes <= glop::table_lds_room(c.filter, c.stride, c.bitmap_log2, c.pt_lg,
+                                                          !c.pt.empty(), !c.bitmap2.empty());
+    if (c.placement == GLOP_PLACE_LDS && !fits)
+        return fail(GLOP_EINVAL, "placement GLOP_PLACE_LDS: the table's " + std::to_string(dense_bytes) +
+                                     " bytes of dense rows do not fit in LDS beside the scan kernel's tables");
+    constexpr uint64_t kAutoLdsTable = 48u << 10;
+    const bool in_lds = c.placement == GLOP_PLACE_LDS || (c.placement == GLOP_PLACE_AUTO && fits &&
+                                                          dense_bytes <= kAutoLdsTable && c.num_patterns > 0);
     const uint64_t o_cls = 0;
     const uint64_t o_bm = align256(o_cls + 256);
     const uint64_t o_delta = align256(o_bm + c.bitmap.size() * 4);
-    const uint64_t o_term = align256(o_delta + c.delta.size() * 4);
+    const uint64_t o_nodes = align256(o_delta + dense_bytes);
+    const uint64_t o_inedge = align256(o_nodes + c.nodes.size() * 8);
+    const uint64_t o_term = align256(o_inedge + c.in_edge.size() * 2);
     const uint64_t o_out = align256(o_term + c.term.size() * 4);
     const uint64_t o_pbytes = align256(o_out + (c.outids.size() + 1) * 4);
     const uint64_t o_poff = align256(o_pbytes + c.pat_bytes.size());
@@ -95,7 +109,9 @@ int upload(glop_dict *h) {
         uint64_t n;
     } pieces[] = {{o_cls, c.cls, 256},
                   {o_bm, c.bitmap.data(), c.bitmap.size() * 4},
-                  {o_delta, c.delta.data(), c.delta.size() * 4},
+                  {o_delta, c.delta.data(), dense_bytes},
+                  {o_nodes, c.nodes.data(), c.nodes.size() * 8},
+                  {o_inedge, c.in_edge.data(), c.in_edge.size() * 2},
                   {o_term, c.term.data(), c.term.size() * 4},
                   {o_out, c.outids.data(), c.outids.size() * 4},
                   {o_pbytes, c.pat_bytes.data(), c.pat_bytes.size()},
@@ -143,6 +159,10 @@ int upload(glop_dict *h) {
     d.pt_probes = c.pt_probes;
     d.pt_depth = c.pt_depth;
     d.pt_leaf = c.pt_leaf;
+    d.n_dense = c.n_dense;
+    d.nodes = c.nodes.empty() ? nullptr : reinterpret_cast<const uint64_t *>(b + o_nodes);
+    d.in_edge = c.in_edge.empty() ? nullptr : reinterpret_cast<const uint16_t *>(b + o_inedge);
+    d.table_lds = in_lds ? 1u : 0u;
     return GLOP_OK;
 }
 
@@ -238,10 +258,12 @@ void tune_file_read_locked() {
         *tab = 0;
         glop_tune_result_t r{};
         int filter = 0;
-        unsigned stride = 0, qgram = 0, lg = 0, pb = 0, tile = 0, prefix = 0;
-        if (std::sscanf(tab + 1, "%d %u %u %u %u %u %u %f %f", &filter, &stride, &qgram, &lg, &pb, &tile, &prefix,
-                        &r.ms, &r.auto_ms) != 9)
+        unsigned stride = 0, qgram = 0, lg = 0, pb = 0, tile = 0, prefix = 0, layout = 0, place = 0;
+        if (std::sscanf(tab + 1, "%d %u %u %u %u %u %u %f %f %u %u", &filter, &stride, &qgram, &lg, &pb, &tile,
+                        &prefix, &r.ms, &r.auto_ms, &layout, &place) < 9)
             continue;
+        r.opts.layout = layout;
+        r.opts.placement = place;
         r.opts.prefix_len = prefix;
         r.opts.filter = filter;
         r.opts.stride = stride;
@@ -259,9 +281,9 @@ void tune_file_append_locked(const std::string &key, const glop_tune_result_t &r
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%d %u %u %u %u %u %u %.6f %.6f\n", key.c_str(), (int)r.opts.filter, r.opts.stride,
+    std::fprintf(f, "%s\t%d %u %u %u %u %u %u %.6f %.6f %u %u\n", key.c_str(), (int)r.opts.filter, r.opts.stride,
                  r.opts.qgram, r.opts.bitmap_log2, r.opts.probe_bits, r.opts.tile_kib, r.opts.prefix_len, r.ms,
-                 r.auto_ms);
+                 r.auto_ms, r.opts.layout, r.opts.placement);
     std::fclose(f);
 }
 
@@ -333,6 +355,7 @@ struct TuneRun {
         o.tile_kib = f.tile_kib;
         o.prefix_len = hd->c.prefix_len ? hd->c.prefix_len : GLOP_PREFIX_FULL;
         o.candidates = 0;
+        o.layout = hd->c.layout;
         hipError_t e = hipMemcpyAsync(bitmap, f.bitmap.data(), f.bitmap.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess && !f.bitmap2.empty())
             e = hipMemcpyAsync(bitmap2, f.bitmap2.data(), f.bitmap2.size() * 4, hipMemcpyHostToDevice, s);
@@ -342,6 +365,13 @@ struct TuneRun {
         a.d = hd->dd;
         a.d.bitmap = bitmap;
         a.d.bitmap2 = f.bitmap2.empty() ? nullptr : bitmap2;
+        // Rows staged in LDS must still fit beside this candidate's filter.
+        if (a.d.table_lds &&
+            (uint64_t)hd->c.n_dense * hd->c.num_classes * 4 >
+                glop::table_lds_room(f.filter, f.stride, f.bitmap_log2, hd->c.pt_lg, !hd->c.pt.empty(),
+                                     !f.bitmap2.empty()))
+            a.d.table_lds = 0;
+        o.placement = a.d.table_lds ? GLOP_PLACE_LDS : GLOP_PLACE_GLOBAL;
         a.d.filter = f.filter;
         a.d.qgram = f.qgram;
         a.d.qmask = f.qmask;
@@ -411,6 +441,8 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
         cur.probe_bits = c.probe_bits;
     }
     cur.tile_kib = c.tile_kib;
+    cur.layout = c.layout;
+    cur.placement = run.h->dd.table_lds ? GLOP_PLACE_LDS : GLOP_PLACE_GLOBAL;
     if (n == 0) {
         out->opts = cur;
         return ok();
@@ -465,9 +497,42 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             best = ms;
         }
     }
+    // Table layout and placement of the chosen engine: the other layout, then
+    // the other placement of the dense rows (LDS only where they fit).  Each is
+    // a handle of its own (the device blob differs), timed with the current
+    // filter options.
+    auto consider_handle = [&](glop_build_opts bo) -> int {
+        glop_dict *hd = make(patterns, lengths, n, &bo, true);
+        if (!hd) return glop_last_error() == GLOP_EINVAL ? GLOP_OK : glop_last_error();
+        glop_build_opts cand = cur;
+        float ms = 0.f;
+        int r = run.time_on(hd, cand, &ms);
+        if (r != GLOP_OK) {
+            glop_free(hd);
+            return r;
+        }
+        if (ms < kKeep * best) {
+            std::swap(run.h, hd);
+            cur = cand;
+            best = ms;
+        }
+        glop_free(hd);
+        return GLOP_OK;
+    };
+    {
+        glop_build_opts bo{};
+        bo.prefix_len = cur.prefix_len;
+        bo.layout = run.h->c.layout == GLOP_LAYOUT_HYBRID ? GLOP_LAYOUT_DENSE : GLOP_LAYOUT_HYBRID;
+        if ((rc = consider_handle(bo)) != GLOP_OK) return rc;
+        bo.layout = run.h->c.layout;
+        bo.placement = run.h->dd.table_lds ? GLOP_PLACE_GLOBAL : GLOP_PLACE_LDS;
+        if ((rc = consider_handle(bo)) != GLOP_OK) return rc;
+    }
     const uint32_t minlen = run.h->c.min_len;
     glop_build_opts none{};
     none.prefix_len = cur.prefix_len;
+    none.layout = cur.layout;
+    none.placement = cur.placement;
     none.filter = GLOP_FILTER_NONE;
     none.tile_kib = 8;
     if ((rc = consider(none)) != GLOP_OK) return rc;
@@ -784,7 +849,10 @@ int glop_get_info(glop_handle_t h, glop_info_t *out) {
     out->max_len = c.max_len;
     out->num_classes = c.num_classes;
     out->num_states = c.num_states;
-    out->table_bytes = (uint64_t)c.delta.size() * 4;
+    out->table_bytes = c.device_table_bytes();
+    out->layout = c.layout;
+    out->placement = h->blob && h->dd.table_lds ? GLOP_PLACE_LDS : GLOP_PLACE_GLOBAL;
+    out->dense_states = c.n_dense;
     out->outlist_ids = c.outids.size();
     out->filter = c.filter;
     out->stride = c.stride;

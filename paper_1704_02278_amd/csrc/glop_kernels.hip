@@ -89,6 +89,7 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
     P.f2_lds_bytes = d.bitmap2 && !P.pt_lds_bytes && d.filter == GLOP_FILTER_QGRAM && d.stride == 1
                          ? (1u << GLOP_FILTER2_LOG2) / 8
                          : 0u;
+    P.tab_lds_bytes = d.table_lds ? d.n_dense * d.num_classes * 4u : 0u;
     P.counts = counts;
     return P;
 }
@@ -99,6 +100,23 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
 using namespace detail;
 
 uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus, kMinTileBytes, 15).bytes; }
+
+uint64_t table_lds_room(int32_t filter, uint32_t stride, uint32_t bitmap_log2, uint32_t pt_lg, bool has_pt,
+                        bool has_f2) {
+    GlopDevDict d{};
+    d.filter = filter;
+    d.stride = stride;
+    d.bitmap_log2 = bitmap_log2;
+    d.pt_lg = pt_lg;
+    d.pt = has_pt ? reinterpret_cast<const uint32_t *>(16) : nullptr;  // presence only, never read
+    d.bitmap2 = has_f2 ? reinterpret_cast<const uint32_t *>(16) : nullptr;
+    const ScanParams P = base_params(d, nullptr);
+    // The single-text layout is the larger of the two (more tiles per item).
+    const uint64_t used = filter == GLOP_FILTER_QGRAM && stride == 4
+                              ? dyn_lds<4, false>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes)
+                              : dyn_lds<1, false>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes);
+    return used < kScanLdsLimit ? kScanLdsLimit - used : 0;
+}
 
 uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes) {
     return batch_geometry(nchunks, max_total_bytes).bytes;

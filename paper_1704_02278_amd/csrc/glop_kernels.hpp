@@ -60,6 +60,12 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream);
 // One-time per-device kernel attribute setup (dynamic LDS above 64 KiB).
 hipError_t prepare_kernels();
 
+// LDS bytes the scan kernel has left, after its other tables, for a copy of
+// the dense transition rows, for a dictionary with these filter and prefix
+// table settings (pt_lg = log2 of the prefix table's slots when has_pt).
+uint64_t table_lds_room(int32_t filter, uint32_t stride, uint32_t bitmap_log2, uint32_t pt_lg, bool has_pt,
+                        bool has_f2);
+
 // Read floor(len / 16) * 16 bytes once (16-byte aligned data) and fold them
 // into *sink: the HBM read-stream ceiling the scan kernel is compared with.
 hipError_t launch_stream_read(const uint8_t *data, uint64_t len, uint64_t *sink, int num_cus, hipStream_t stream);

@@ -116,14 +116,20 @@ static_assert((1u << GLOP_FILTER2_LOG2) / 8 <= pt_lds_cap<1>(), "second filter e
 template <bool BATCH>
 constexpr uint32_t item_tiles_cap() { return BATCH ? kMaxBatchTilesPerItem : kMaxTilesPerItem; }
 
+// Dynamic LDS the scan kernels may use (the workgroup's 160 KiB less room for
+// their few static words).
+constexpr uint32_t kScanLdsLimit = 160u * 1024u - 1024u;
+
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
 // per-tile matched-start counts | per-tile record counts | prefix table or
-// second filter (scan kernel, when staged; never both).
+// second filter (scan kernel, when staged; never both) | dense transition
+// rows (scan kernel, when placed in LDS).
 template <int STRIDE, bool BATCH>
 struct LdsLayout {
     uint32_t bm_bytes;
     uint32_t pt_bytes = 0;
     uint32_t f2_bytes = 0;
+    uint32_t tab_bytes = 0;
     __host__ __device__ constexpr uint32_t cls_off() const { return bm_bytes; }
     __host__ __device__ constexpr uint32_t ring_off() const { return bm_bytes + 256; }
     __host__ __device__ constexpr uint32_t hits_off() const { return ring_off() + kWaves * ring_cap<STRIDE>() * 2; }
@@ -131,7 +137,8 @@ struct LdsLayout {
     __host__ __device__ constexpr uint32_t rec_off() const { return nm_off() + item_tiles_cap<BATCH>() * 4; }
     __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + item_tiles_cap<BATCH>() * 8; }
     __host__ __device__ constexpr uint32_t f2_off() const { return pt_off() + pt_bytes; }
-    __host__ __device__ constexpr uint32_t bytes() const { return f2_off() + f2_bytes; }
+    __host__ __device__ constexpr uint32_t tab_off() const { return f2_off() + f2_bytes; }
+    __host__ __device__ constexpr uint32_t bytes() const { return tab_off() + tab_bytes; }
 };
 
 // A text as the kernels see it: coordinates x count bytes from abase, the
@@ -167,6 +174,7 @@ struct ScanParams {
     uint32_t bm_bytes;           // bitmap bytes staged in LDS (0 without filter)
     uint32_t pt_lds_bytes;       // prefix table bytes the scan kernel stages in LDS (0: the walks start at the root)
     uint32_t f2_lds_bytes;       // second filter bytes the scan kernel stages in LDS (0: none)
+    uint32_t tab_lds_bytes;      // dense transition rows the scan kernel stages in LDS (0: read from memory)
     uint64_t *tile_rec;          // records per tile
     uint32_t *tile_nm;           // matched starts per tile
     uint64_t *staging;           // kStageCap per tile: stage_entry() words
@@ -359,7 +367,7 @@ __device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32
         const uint32_t h = glop_hash1(g);
         // Both bits set, written as "no bit of the pair missing" so the two
         // one-bit masks feed a single three-input logic op.
-        return (~bm[h >> (sh + 5u)] & glop_block_bits(h)) == 0u ? 1u : 0u;
+        return (~bm[h >> (sh + 5u)] & glop_block_bits(g)) == 0u ? 1u : 0u;
     }
     const uint32_t s1 = glop_hash1(g) >> sh;
     uint32_t hit = bm[s1 >> 5] >> (s1 & 31);
@@ -374,17 +382,20 @@ __device__ __forceinline__ uint32_t probe(const uint32_t *bm, uint32_t g, uint32
 // into each accumulator) enters at the top of a1/a2 as their contents move
 // down one place (v_alignbit).  After 16 probes, bit 16 + u of a1 & a2 is
 // probe u's result.  A shift takes its amount modulo 32, so the tested bit
-// needs no mask and no compare: about 10 vector instructions per probe where
-// a 0/1 result costs 12 to 13.
+// needs no mask and no compare.  For K = 3, `g1` holds the key's second byte
+// in its low byte: at stride 1 with q = 4 that is the next offset's key,
+// already in a register, so the blocked probe costs a hash, two instructions
+// of address, the read, and two shift + align pairs.
 template <int K, bool Q4>
-__device__ __forceinline__ void probe_acc(const uint32_t *bm, uint32_t g, uint32_t qmask, uint32_t sh,
+__device__ __forceinline__ void probe_acc(const uint32_t *bm, uint32_t g, uint32_t g1, uint32_t qmask, uint32_t sh,
                                           uint32_t &a1, uint32_t &a2) {
     if (!Q4) g &= qmask;
     if (K == 3) {
+        if (!Q4) g1 = g >> 8;  // the masked key's second byte (0 when q = 1)
         const uint32_t h = glop_hash1(g);
         const uint32_t w = bm[h >> (sh + 5u)];
-        a1 = __builtin_amdgcn_alignbit(w >> ((h >> 8) & 31u), a1, 1u);
-        a2 = __builtin_amdgcn_alignbit(w >> ((h >> 13) & 31u), a2, 1u);
+        a1 = __builtin_amdgcn_alignbit(w >> (g & 31u), a1, 1u);
+        a2 = __builtin_amdgcn_alignbit(w >> (g1 & 31u), a2, 1u);
         return;
     }
     const uint32_t s1 = glop_hash1(g) >> sh;
@@ -417,13 +428,26 @@ __device__ __forceinline__ uint64_t text_u64(const Span &s, uint64_t z) {
     return (lo >> sh) | (hi << (64u - sh));
 }
 
-// What a walk reads besides the transition table: the byte classes and the
-// prefix table, both in LDS (the table is null when the dictionary has none,
-// when it is too large for LDS, and in the emit kernel's rare rescans).
+// What a walk reads from LDS: the byte classes, the prefix table (null when
+// the dictionary has none, when it is too large for LDS, and in the emit
+// kernel's rare rescans) and a copy of the dense transition rows (null: the
+// rows are read from device memory).
 struct WalkTabs {
     const uint8_t *cls;
     const uint4 *pt;
+    const uint32_t *delta = nullptr;
 };
+
+// One transition from state st on class c: the next state | GLOP_TERM_BIT, or
+// 0 (no edge).  Dense rows come from LDS when staged there, else from device
+// memory; deeper states of the hybrid layout from their nodes.
+__device__ __forceinline__ uint32_t next_state(const GlopDevDict &d, const WalkTabs &tabs, uint32_t st, uint32_t c) {
+    if (st < d.n_dense) {
+        const uint64_t idx = (uint64_t)st * d.num_classes + c;
+        return tabs.delta ? tabs.delta[idx] : d.delta[idx];
+    }
+    return glop_node_step(d.nodes, d.in_edge, d.n_dense, st, c);
+}
 
 // The prefix table's entry for a key (0: no pattern begins so); one 16-byte
 // read per slot.
@@ -443,7 +467,6 @@ __device__ __forceinline__ uint32_t prefix_entry(const GlopDevDict &d, const uin
 // come 8 at a time from aligned loads; the walk may run past its tile up to
 // the end of its text.
 __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, const WalkTabs &tabs, uint64_t x) {
-    const uint32_t C = d.num_classes;
     uint32_t st = 0, last = 0;
     if (tabs.pt) {
         // The first D steps in one lookup.  Every pattern is at least D bytes
@@ -477,7 +500,7 @@ __device__ __forceinline__ uint32_t walk(const GlopDevDict &d, const Span &s, co
         const uint32_t c = tabs.cls[win & 0xFFu];
         win >>= 8;
         --have;
-        const uint32_t e = d.delta[(uint64_t)st * C + c];
+        const uint32_t e = next_state(d, tabs, st, c);
         if (e == 0) break;
         st = e & GLOP_STATE_MASK;
         if (e & GLOP_TERM_BIT) last = st;
@@ -645,16 +668,71 @@ struct StageSink {
     }
 };
 
+// Per-pattern counts of the emit kernel, gathered per workgroup first: a small
+// LDS table keyed by pattern id (open addressing, a few probes, claimed by
+// compare-and-swap) takes the increments, and each work item's distinct ids
+// then go to the global counts with one atomic add each.  Short patterns that
+// occur all over a log text would otherwise put thousands of same-address
+// atomics on a few L2 lines.  An id that finds no slot adds to the global
+// count directly.  A count stays below 2^32: an item holds at most
+// kMaxTilesPerItem * 8 KiB offsets and a pattern occurs once per offset.
+struct CountTable {
+    static constexpr uint32_t kLog2 = 11;
+    static constexpr uint32_t kSlots = 1u << kLog2;
+    static constexpr int kProbes = 8;
+    uint32_t *key;   // id + 1, 0 = free
+    uint32_t *val;
+    uint64_t *counts;
+
+    __device__ __forceinline__ void add(uint32_t id) const {
+        const uint32_t want = id + 1u;
+        uint32_t s = (id * 0x9E3779B1u) >> (32u - kLog2);
+        for (int p = 0; p < kProbes; ++p) {
+            uint32_t k = __hip_atomic_load(&key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == 0u) {
+                k = atomicCAS(&key[s], 0u, want);
+                if (k == 0u) k = want;
+            }
+            if (k == want) {
+                atomicAdd(&val[s], 1u);
+                return;
+            }
+            s = (s + 1u) & (kSlots - 1u);
+        }
+        atomicAdd(reinterpret_cast<unsigned long long *>(counts + id), 1ull);
+    }
+    // Clear every slot (the whole workgroup; a barrier must follow).
+    __device__ __forceinline__ void clear() const {
+        for (uint32_t k = threadIdx.x; k < kSlots; k += kBlock) {
+            key[k] = 0u;
+            val[k] = 0u;
+        }
+    }
+    // Add the gathered counts to the global ones and clear the table (the
+    // whole workgroup, between barriers).
+    __device__ __forceinline__ void flush() const {
+        for (uint32_t k = threadIdx.x; k < kSlots; k += kBlock) {
+            const uint32_t id1 = key[k];
+            if (id1) {
+                atomicAdd(reinterpret_cast<unsigned long long *>(counts + (id1 - 1u)), (unsigned long long)val[k]);
+                key[k] = 0u;
+                val[k] = 0u;
+            }
+        }
+    }
+};
+
 // Sink of the emit kernel's rescan: write the records directly, in order.
 template <bool BATCH>
 struct DirectSink {
     const EmitParams *E;
+    const CountTable *ct;
     uint64_t base;         // output position of the tile's first record
     uint64_t chunk_first;  // output position of its chunk's first record (batch)
     uint64_t cursor = 0;   // records written so far in the tile
 
-    __device__ __forceinline__ DirectSink(const EmitParams *e, uint64_t b, uint64_t f)
-        : E(e), base(b), chunk_first(f) {}
+    __device__ __forceinline__ DirectSink(const EmitParams *e, const CountTable *c, uint64_t b, uint64_t f)
+        : E(e), ct(c), base(b), chunk_first(f) {}
 
     __device__ __forceinline__ void batch(const ScanParams &P, uint64_t, const TileInfo &ti, uint32_t off,
                                           uint32_t last) {
@@ -673,7 +751,7 @@ struct DirectSink {
                 if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
                 const uint64_t pos = base + cursor + excl + j++;
                 put_record<BATCH>(*E, pos, chunk_first, glop_match_t{i, id, ti.chunk});
-                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                ct->add(id);
             }
         }
         cursor += tot;
@@ -700,10 +778,10 @@ __device__ __forceinline__ void tile_hits4(const GlopDevDict &d, const TileRegs<
         uint32_t a1 = 0, a2 = K == 1 ? ~0u : 0u;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            probe_acc<K, Q4>(bm, r.v[k].x, qmask, sh, a1, a2);
-            probe_acc<K, Q4>(bm, r.v[k].y, qmask, sh, a1, a2);
-            probe_acc<K, Q4>(bm, r.v[k].z, qmask, sh, a1, a2);
-            probe_acc<K, Q4>(bm, r.v[k].w, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].x, r.v[k].x >> 8, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].y, r.v[k].y >> 8, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].z, r.v[k].z >> 8, qmask, sh, a1, a2);
+            probe_acc<K, Q4>(bm, r.v[k].w, r.v[k].w >> 8, qmask, sh, a1, a2);
             __asm__ volatile("" : "+v"(a1), "+v"(a2));
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -927,12 +1005,62 @@ __device__ __forceinline__ bool list_offsets1(const HitList &L, uint32_t t_rel, 
 //
 // Bit u of round k's 16-bit mask (word k/2, half k%2) marks offset
 // x0 + k*1024 + lane*16 + u as not ruled out.
+
+// The second filter's three bits for key g (double hashing: the top bits of h,
+// k and h + k); bit 0 of the result is 1 if all three are set.
+__device__ __forceinline__ uint32_t filter2_bits(const uint32_t *bm2, uint32_t g) {
+    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h), hk = h + k;
+    constexpr uint32_t sh2 = 32u - GLOP_FILTER2_LOG2;
+    return (bm2[h >> (sh2 + 5u)] >> ((h >> sh2) & 31u)) & (bm2[k >> (sh2 + 5u)] >> ((k >> sh2) & 31u)) &
+           (bm2[hk >> (sh2 + 5u)] >> ((hk >> sh2) & 31u));
+}
+
+// Per-wave staging of the second filter (stride 1), in the wave's LDS ring,
+// which is otherwise used only after the tile's masks are known: a ring of
+// (key, offset in tile) pairs waiting for the second filter, and one word per
+// lane and round pair collecting the bits the second filter rejects.
+struct Stage2 {
+    static constexpr uint32_t kEntries = 128;  // at most 63 waiting + 64 added at once
+    uint2 *ent;    // kEntries
+    uint32_t *rej; // kWave * 4 words: lane L, rounds 2j and 2j+1 -> rej[L * 4 + j]
+};
+static_assert(Stage2::kEntries * 8 + kWave * 4 * 4 <= kRing1 * 2, "second-filter staging exceeds the wave's ring");
+
+// The second filter on n staged entries from `head` (n <= 64, one per lane):
+// a rejected offset's bit is set in its owner lane's reject word.
+template <bool Q4>
+__device__ __forceinline__ void filter2_batch(const Stage2 &st, const uint32_t *bm2, uint32_t qmask, uint32_t head,
+                                              uint32_t n) {
+    const uint32_t lane = lane_id();
+    if (lane < n) {
+        const uint2 e = st.ent[(head + lane) & (Stage2::kEntries - 1)];
+        const uint32_t g = Q4 ? e.x : e.x & qmask;
+        if ((filter2_bits(bm2, g) & 1u) == 0u) {
+            const uint32_t off = e.y;  // k * 1024 + owner * 16 + u
+            const uint32_t owner = (off >> 4) & (kWave - 1), k = off >> 10;
+            atomicOr(&st.rej[owner * 4 + (k >> 1)], 1u << ((k & 1u) * 16u + (off & 15u)));
+        }
+    }
+}
+
 template <int R, bool FILTER, int K, bool Q4>
 __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo &ti, const TileRegs<R> &r,
-                                            const uint32_t *bm, const uint32_t *bm2, uint32_t (&m)[R / 2]) {
+                                            const uint32_t *bm, const uint32_t *bm2, uint32_t (&m)[R / 2],
+                                            const Stage2 *st = nullptr) {
+    static_assert(R / 2 <= 4, "reject words hold four round pairs");
     const uint32_t lane = lane_id();
     const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
     const bool full = ti.x0 >= ti.s.head && ti.x0 + R * kRoundBytes <= ti.s.valid_end;
+    // Second filter, for the few offsets the first one lets through: their
+    // keys wait in the staging ring and are checked 64 at a time, one per
+    // lane, instead of each lane looping over its own survivors while the
+    // wave waits for the lane with the most.
+    const bool f2 = FILTER && bm2 != nullptr && st != nullptr;
+    uint32_t head = 0, tail = 0;  // wave-uniform ring indices
+    if (f2) {
+        reinterpret_cast<uint4 *>(st->rej)[lane] = make_uint4(0u, 0u, 0u, 0u);
+        wave_lds_sync();
+    }
 #pragma unroll
     for (int k = 0; k < R / 2; ++k) m[k] = 0;
 #pragma unroll
@@ -947,11 +1075,13 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
             if (lane == kWave - 1) nx = next0;
             const uint32_t w[5] = {r.v[k].x, r.v[k].y, r.v[k].z, r.v[k].w, nx};
             uint32_t a1 = 0, a2 = K == 1 ? ~0u : 0u;
+            // Key of offset u (u = 16 is the next lane's first word).
+            auto key = [&](int u) -> uint32_t {
+                return (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3) : w[u >> 2];
+            };
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                const uint32_t g = (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3)
-                                           : w[u >> 2];
-                probe_acc<K, Q4>(bm, g, qmask, sh, a1, a2);
+                probe_acc<K, Q4>(bm, key(u), key(u + 1), qmask, sh, a1, a2);
                 if ((u & 3) == 3) {
                     // Finish these probes here (see tile_hits4).
                     __asm__ volatile("" : "+v"(a1), "+v"(a2));
@@ -959,34 +1089,54 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
                 }
             }
             mask = (a1 & a2) >> 16;
-            // Second filter, for the few offsets the first one let through
-            // (a lane loops over its own survivors; most lanes have none).
-            if (bm2) {
+            if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
+            if (f2) {
+                // Stage the survivors' keys: each pass adds every lane's next
+                // survivor; 64 waiting entries are checked at once.
                 uint32_t left = mask;
-                while (left) {
-                    const uint32_t u = (uint32_t)__builtin_ctz(left);
-                    left &= left - 1u;
-                    // Word pair (w[a], w[a+1]), a = u / 4, picked in two steps.
-                    const bool up = (u & 8u) != 0, odd = (u & 4u) != 0;
-                    const uint32_t p0 = up ? w[2] : w[0], p1 = up ? w[3] : w[1], p2 = up ? w[4] : w[2];
-                    uint32_t g = __builtin_amdgcn_alignbyte(odd ? p2 : p1, odd ? p1 : p0, u & 3u);
-                    if (!Q4) g &= qmask;
-                    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h), hk = h + k;
-                    constexpr uint32_t sh2 = 32u - GLOP_FILTER2_LOG2;
-                    const uint32_t all = (bm2[h >> (sh2 + 5u)] >> ((h >> sh2) & 31u)) &
-                                         (bm2[k >> (sh2 + 5u)] >> ((k >> sh2) & 31u)) &
-                                         (bm2[hk >> (sh2 + 5u)] >> ((hk >> sh2) & 31u));
-                    // Bit u of the mask becomes bit 0 of `all` (one v_bfi).
-                    const uint32_t bit = 1u << u;
-                    mask = (mask & ~bit) | ((all << u) & bit);
+                for (;;) {
+                    const uint64_t bal = __ballot(left != 0u);
+                    if (bal == 0) break;
+                    if (left) {
+                        const uint32_t u = (uint32_t)__builtin_ctz(left);
+                        left &= left - 1u;
+                        // Word pair (w[a], w[a+1]), a = u / 4, picked in two steps.
+                        const bool up = (u & 8u) != 0, odd = (u & 4u) != 0;
+                        const uint32_t p0 = up ? w[2] : w[0], p1 = up ? w[3] : w[1], p2 = up ? w[4] : w[2];
+                        // (v_alignbyte reads only the low two bits of its shift.)
+                        const uint32_t g = __builtin_amdgcn_alignbyte(odd ? p2 : p1, odd ? p1 : p0, u);
+                        const uint32_t pos =
+                            tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        st->ent[pos & (Stage2::kEntries - 1)] = make_uint2(g, (uint32_t)k * kRoundBytes + lane * 16u + u);
+                    }
+                    tail += (uint32_t)__popcll(bal);
+                    if (tail - head >= (uint32_t)kWave) {
+                        wave_lds_sync();
+                        filter2_batch<Q4>(*st, bm2, qmask, head, kWave);
+                        head += kWave;
+                    }
                 }
             }
+        } else if (!full) {
+            mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
         }
-        if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
         m[k / 2] |= mask << (16 * (k % 2));
         // Keep rounds apart: interleaving all probes of the tile costs more
         // registers than the wave has.
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f2) {
+        if (tail != head) {
+            wave_lds_sync();
+            filter2_batch<Q4>(*st, bm2, qmask, head, tail - head);
+        }
+        wave_lds_sync();
+        const uint4 rj = reinterpret_cast<const uint4 *>(st->rej)[lane];
+        const uint32_t rw[4] = {rj.x, rj.y, rj.z, rj.w};
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) m[k] &= ~rw[k];
+        wave_lds_sync();  // the ring is free again (reads done before anyone writes it)
     }
 }
 
@@ -1090,7 +1240,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     __shared__ uint32_t hl_count, item_failed, tile_next, hl_walked;
     __shared__ uint64_t item_sh;
     __shared__ uint64_t red[kWaves];
-    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes};
+    const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes, P.tab_lds_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -1122,7 +1272,17 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             bm2 = reinterpret_cast<const uint32_t *>(lds + Lo.f2_off());
         }
     }
-    const WalkTabs tabs{cls, pt};
+    const uint32_t *tab = nullptr;
+    if (P.tab_lds_bytes) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(P.d.delta);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds + Lo.tab_off());
+        for (uint32_t k = threadIdx.x; k < P.tab_lds_bytes / 16; k += kBlock) dst[k] = src[k];
+        uint32_t *dst4 = reinterpret_cast<uint32_t *>(lds + Lo.tab_off());
+        for (uint32_t k = (P.tab_lds_bytes / 16) * 4 + threadIdx.x; k < P.tab_lds_bytes / 4; k += kBlock)
+            dst4[k] = P.d.delta[k];
+        tab = dst4;
+    }
+    const WalkTabs tabs{cls, pt, tab};
 
     const uint64_t nt = total_tiles<BATCH>(P);
     // First work item: a device ticket for a batch, the block index otherwise.
@@ -1183,7 +1343,9 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 }
             } else {
                 uint32_t m[R / 2];
-                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, bm2, m);
+                const Stage2 st2{reinterpret_cast<uint2 *>(queue),
+                                 reinterpret_cast<uint32_t *>(queue) + 2 * Stage2::kEntries};
+                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, bm2, m, &st2);
                 if (has_next) load_tile<R, FILTER>(nxt, r);
                 // Survivors wait in the workgroup list, so walks run in full
                 // batches of 64 instead of one short batch per tile.  Here the
@@ -1260,6 +1422,9 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     // chunk that began before the item.
     __shared__ uint64_t tile_first[BATCH ? kMaxBatchTilesPerItem : 1];
     __shared__ uint64_t carry_first;
+    __shared__ uint32_t count_key[CountTable::kSlots];
+    __shared__ uint32_t count_val[CountTable::kSlots];
+    const CountTable ct{count_key, count_val, P.counts};
     const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes};
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
@@ -1276,6 +1441,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         any_failed = call_base == kItemFailed ? 1u : 0u;  // an earlier piece failed
         any_over = 0;
     }
+    ct.clear();
     __syncthreads();
 
     // Thread-0 steps inside the loop sit between barriers of the same item
@@ -1369,7 +1535,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                                 bits &= bits - 1u;
                                 const uint32_t id = P.d.outids[low + k];
                                 put_record<BATCH>(E, pos, cf, glop_match_t{i, id, ti.chunk});
-                                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                                ct.add(id);
                                 ++pos;
                             }
                         } else {
@@ -1378,7 +1544,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                                 const uint32_t id = P.d.outids[first + k];
                                 if (P.d.verify_from && !verified(P.d, ti.s, x, id)) continue;
                                 put_record<BATCH>(E, pos, cf, glop_match_t{i, id, ti.chunk});
-                                atomicAdd(reinterpret_cast<unsigned long long *>(P.counts + id), 1ull);
+                                ct.add(id);
                                 ++pos;
                             }
                         }
@@ -1389,7 +1555,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             for (uint32_t o = wave; o < n_over; o += kWaves) {
                 const uint64_t ot = over_tile[o];
                 const TileInfo ti = tile_info<BATCH, TILE>(P, ot);
-                DirectSink<BATCH> sink(&E, over_base[o], chunk_first_pos(ti.chunk));
+                DirectSink<BATCH> sink(&E, &ct, over_base[o], chunk_first_pos(ti.chunk));
                 // Two rounds at a time, in order, through one sink: a rare
                 // path that keeps a quarter of the tile in registers (the whole
                 // tile would push the kernel past its register budget).
@@ -1412,6 +1578,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             last_total = base;
         }
         if (threadIdx.x == 0) any_over = 0;  // every read of it preceded the last barrier
+        ct.flush();  // every add of the item preceded the last barrier
         __syncthreads();
     }
     if (has_last && threadIdx.x == 0) {
@@ -1554,18 +1721,26 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) 
 }
 
 template <int STRIDE, bool BATCH>
-constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes, uint32_t f2_bytes = 0) {
-    return LdsLayout<STRIDE, BATCH>{bm_bytes, pt_bytes, f2_bytes}.bytes();
+constexpr size_t dyn_lds(uint32_t bm_bytes, uint32_t pt_bytes, uint32_t f2_bytes = 0, uint32_t tab_bytes = 0) {
+    return LdsLayout<STRIDE, BATCH>{bm_bytes, pt_bytes, f2_bytes, tab_bytes}.bytes();
+}
+
+// The emit kernel uses the bitmap, the byte classes and the per-wave rings of
+// the layout (for its rare rescans), nothing after them.
+template <int STRIDE, bool BATCH>
+constexpr size_t emit_dyn_lds(uint32_t bm_bytes) {
+    return LdsLayout<STRIDE, BATCH>{bm_bytes}.hits_off();
 }
 
 template <int STRIDE, bool FILTER, int K, bool Q4, int R>
 struct Kernels {
     static hipError_t set_lds_limit() {
-        // The scan kernels may stage a prefix table; the emit kernels never do.
+        // The scan kernels may stage a prefix table or second filter and the
+        // dense rows (a launch checks its own size); the emit kernels never do.
         constexpr uint32_t bm = (1u << 19) / 8;
-        const int bytes[4] = {(int)dyn_lds<STRIDE, false>(bm, pt_lds_cap<STRIDE>()),
-                              (int)dyn_lds<STRIDE, true>(bm, pt_lds_cap<STRIDE>()), (int)dyn_lds<STRIDE, false>(bm, 0),
-                              (int)dyn_lds<STRIDE, true>(bm, 0)};
+        static_assert(dyn_lds<STRIDE, false>(bm, pt_lds_cap<STRIDE>()) <= kScanLdsLimit, "scan layout exceeds LDS");
+        const int bytes[4] = {(int)kScanLdsLimit, (int)kScanLdsLimit, (int)emit_dyn_lds<STRIDE, false>(bm),
+                              (int)emit_dyn_lds<STRIDE, true>(bm)};
         const void *fns[] = {reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>),
                              reinterpret_cast<const void *>(&glop_scan_kernel<STRIDE, FILTER, K, Q4, R, true>),
                              reinterpret_cast<const void *>(&glop_emit_kernel<STRIDE, FILTER, K, Q4, R, false>),
@@ -1579,8 +1754,9 @@ struct Kernels {
 
     static hipError_t one(const ScanParams &P, const EmitParams &E, uint32_t grid, hipStream_t s,
                           const glop_events_t *ev) {
-        const size_t lds = dyn_lds<STRIDE, false>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes);
-        const size_t emit_lds = dyn_lds<STRIDE, false>(P.bm_bytes, 0);
+        const size_t lds = dyn_lds<STRIDE, false>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes, P.tab_lds_bytes);
+        if (lds > kScanLdsLimit) return hipErrorInvalidValue;
+        const size_t emit_lds = emit_dyn_lds<STRIDE, false>(P.bm_bytes);
         hipError_t e;
         if (ev && ev->scan_begin && (e = hipEventRecord((hipEvent_t)ev->scan_begin, s)) != hipSuccess) return e;
         hipLaunchKernelGGL((glop_scan_kernel<STRIDE, FILTER, K, Q4, R, false>), dim3(grid), dim3(kBlock), lds, s, P);
@@ -1595,8 +1771,9 @@ struct Kernels {
 
     static hipError_t batch(const ScanParams &P, const EmitParams &E, uint64_t *chunk_count, uint64_t *total,
                             int num_cus, hipStream_t s) {
-        const size_t lds = dyn_lds<STRIDE, true>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes);
-        const size_t emit_lds = dyn_lds<STRIDE, true>(P.bm_bytes, 0);
+        const size_t lds = dyn_lds<STRIDE, true>(P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes, P.tab_lds_bytes);
+        if (lds > kScanLdsLimit) return hipErrorInvalidValue;
+        const size_t emit_lds = emit_dyn_lds<STRIDE, true>(P.bm_bytes);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);
         const uint64_t items = (P.tile_cap + P.tiles_per_item - 1) / P.tiles_per_item;

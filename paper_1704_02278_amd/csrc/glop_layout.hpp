@@ -18,6 +18,22 @@
 // only the deepest terminal it passed and emits that one list, which is already
 // in id order.
 //
+// Hybrid layout (GLOP_LAYOUT_HYBRID): only the rows of states below n_dense
+// (those of depth <= 2, a prefix of the breadth-first numbering) are dense.
+// Breadth-first numbering gives the children of a state consecutive ids in
+// class order, so a deeper state s is described by one 64-bit node,
+// nodes[s - n_dense]:
+//   bits 0..31  first child's id (children: first .. first + count - 1)
+//   bits 32..39 number of children
+//   bits 40..47 the class of the edge to the only child (count == 1)
+//   bit  48     the only child is terminal (count == 1)
+// and, for every state c >= n_dense, in_edge[c - n_dense] = the class of the
+// edge into c | (c is terminal) << 8, which a state with several children
+// scans.  Every child of a state at or past n_dense is itself past n_dense.
+#define GLOP_NODE_COUNT_SHIFT 32u
+#define GLOP_NODE_CLASS_SHIFT 40u
+#define GLOP_NODE_TERM_SHIFT 48u
+//
 // Filter: a Bloom filter of 2^bitmap_log2 bits.  For every pattern p and
 // every t in [0, stride), the q bytes p[t .. t+q) (little-endian in a 32-bit
 // word g, zero above q bytes) set bit glop_slot1(g) and, with two probe bits,
@@ -66,7 +82,9 @@
 // v_mad_u32_u24 on CDNA): the product mixes the low three bytes upwards and the
 // added key brings the fourth byte into the top bits that pick the slot.  The
 // second hash first rotates the key by one byte.  Slots are the top
-// bitmap_log2 bits.
+// bitmap_log2 bits.  The multipliers are 24-bit truncations of well-mixed odd
+// constants: the golden ratio times 2^24 (0x9E3779) and MurmurHash3's 32-bit
+// finaliser multipliers 0x85EBCA6B and 0xC2B2AE35.
 GLOP_HD uint32_t glop_hash1(uint32_t g) { return (g & 0xFFFFFFu) * 0x9E3779u + g; }
 GLOP_HD uint32_t glop_hash2(uint32_t g) {
     const uint32_t r = (g >> 8) | (g << 24);
@@ -80,10 +98,15 @@ GLOP_HD uint32_t glop_f2_mix(uint32_t h) { return ((h >> 8) & 0xFFFFFFu) * 0xC2B
 
 // Blocked variant (probe_bits 3): both bits of a q-gram lie in one 32-bit word,
 // so a probe is one hash and one LDS read.  The word comes from the top
-// bitmap_log2 - 5 bits of glop_hash1, the two bit positions from bits 8..12
-// and 13..17 (well mixed by the multiply; the word index uses none of them).
+// bitmap_log2 - 5 bits of glop_hash1 (which mixes every byte of the key); the
+// two bit positions are the low five bits of the key's first and second bytes
+// (0 for the second when q = 1).  A shift takes its amount modulo 32, so the
+// kernels test those bits by shifting the word by the key itself and by the
+// key one byte on, with no instruction to extract the positions.  (On 15,699
+// 4-byte keys in log text this passes 0.667 % of offsets against 0.681 % for
+// positions taken from hash bits 8..17.)
 GLOP_HD uint32_t glop_block_word(uint32_t h, uint32_t bitmap_log2) { return h >> (37u - bitmap_log2); }
-GLOP_HD uint32_t glop_block_bits(uint32_t h) { return (1u << ((h >> 8) & 31u)) | (1u << ((h >> 13) & 31u)); }
+GLOP_HD uint32_t glop_block_bits(uint32_t g) { return (1u << (g & 31u)) | (1u << ((g >> 8) & 31u)); }
 
 // Home slot of a prefix-table key: the high word folded into the low one,
 // then Knuth's multiplicative hash (the golden ratio times 2^32), top pt_lg
@@ -92,8 +115,25 @@ GLOP_HD uint32_t glop_pt_slot(uint32_t lo, uint32_t hi, uint32_t pt_lg) {
     return ((lo ^ (hi * 0x85EBCA6Bu)) * 0x9E3779B1u) >> (32u - pt_lg);
 }
 
+// One step of the walk below the dense rows (hybrid layout): the next state
+// with GLOP_TERM_BIT, or 0 when state s has no edge of class k.
+GLOP_HD uint32_t glop_node_step(const uint64_t *nodes, const uint16_t *in_edge, uint32_t n_dense, uint32_t s,
+                                uint32_t k) {
+    const uint64_t node = nodes[s - n_dense];
+    const uint32_t first = (uint32_t)node, count = (uint32_t)(node >> GLOP_NODE_COUNT_SHIFT) & 0xFFu;
+    if (count == 1u) {
+        if (((uint32_t)(node >> GLOP_NODE_CLASS_SHIFT) & 0xFFu) != k) return 0u;
+        return first | ((uint32_t)(node >> GLOP_NODE_TERM_SHIFT) & 1u) * GLOP_TERM_BIT;
+    }
+    for (uint32_t j = 0; j < count; ++j) {
+        const uint32_t e = in_edge[first + j - n_dense];
+        if ((e & 0xFFu) == k) return (first + j) | ((e >> 8) & 1u) * GLOP_TERM_BIT;
+    }
+    return 0u;
+}
+
 struct GlopDevDict {
-    const uint32_t *delta;   // num_states * num_classes
+    const uint32_t *delta;   // n_dense * num_classes (every row with the dense layout)
     const uint32_t *term;    // 2 * num_states: (first, count) per state
     const uint32_t *outids;  // output lists
     const uint32_t *bitmap;  // 2^bitmap_log2 bits
@@ -116,4 +156,10 @@ struct GlopDevDict {
     uint32_t pt_lg, pt_probes;
     uint32_t pt_depth;         // D: 4 or 8
     uint32_t pt_leaf;          // 1 if the trie ends at depth D (the lookup is the walk)
+    // Transition table layout (see above): states below n_dense have dense
+    // rows; with the hybrid layout the others have nodes.
+    uint32_t n_dense;
+    const uint64_t *nodes;     // null with the dense layout
+    const uint16_t *in_edge;
+    uint32_t table_lds;        // 1: the scan kernel stages the dense rows in LDS
 };

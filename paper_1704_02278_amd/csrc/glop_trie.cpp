@@ -14,7 +14,9 @@ namespace glop {
 
 namespace {
 
-constexpr uint64_t kMaxTableBytes = 16ull << 30;  // dense table ceiling on the device
+constexpr uint64_t kMaxTableBytes = 16ull << 30;  // dense table ceiling (host rows)
+constexpr uint64_t kAutoHybridBytes = 32ull << 20; // automatic layout: hybrid above this dense size
+constexpr uint32_t kDenseDepth = 2;                // hybrid: dense rows for depth <= 2
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 uint32_t ceil_log2(uint64_t v) {
@@ -104,7 +106,61 @@ uint32_t auto_prefix_len(const uint8_t *const *patterns, const uint32_t *lengths
     return kLen;
 }
 
+// Hybrid layout (glop_layout.hpp): dense rows for the states of depth <=
+// kDenseDepth, a node per deeper state.  Breadth-first numbering makes those
+// states a prefix of the ids and every state's children consecutive.
+int build_hybrid(Compiled &c, std::string &err) {
+    const uint64_t S = c.num_states;
+    const uint32_t C = c.num_classes;
+    std::vector<uint8_t> depth(S, 0);
+    uint64_t n_dense = S;
+    for (uint64_t s = 0; s < S; ++s) {
+        if (depth[s] > kDenseDepth && n_dense == S) n_dense = s;
+        for (uint32_t k = 1; k < C; ++k) {
+            const uint32_t e = c.delta[s * C + k];
+            if (e) depth[e & GLOP_STATE_MASK] = (uint8_t)std::min<uint32_t>(depth[s] + 1u, 255u);
+        }
+    }
+    c.n_dense = (uint32_t)n_dense;
+    c.nodes.assign(S - n_dense, 0ull);
+    c.in_edge.assign(S - n_dense, 0u);
+    for (uint64_t s = 0; s < S; ++s) {
+        uint32_t first = 0, count = 0, k1 = 0, e1 = 0;
+        for (uint32_t k = 1; k < C; ++k) {
+            const uint32_t e = c.delta[s * C + k];
+            if (!e) continue;
+            const uint32_t ch = e & GLOP_STATE_MASK;
+            if (count == 0) {
+                first = ch;
+                k1 = k;
+                e1 = e;
+            } else if (ch != first + count) {
+                err = "internal: children are not numbered consecutively";
+                return GLOP_EINTERNAL;
+            }
+            ++count;
+            if (ch >= n_dense) c.in_edge[ch - n_dense] = (uint16_t)(k | ((e & GLOP_TERM_BIT) ? 0x100u : 0u));
+            else if (s >= n_dense) {
+                err = "internal: a dense state below a node";
+                return GLOP_EINTERNAL;
+            }
+        }
+        if (s < n_dense) continue;
+        uint64_t node = (uint64_t)first | ((uint64_t)count << GLOP_NODE_COUNT_SHIFT);
+        if (count == 1)
+            node |= ((uint64_t)k1 << GLOP_NODE_CLASS_SHIFT) |
+                    ((uint64_t)((e1 & GLOP_TERM_BIT) ? 1u : 0u) << GLOP_NODE_TERM_SHIFT);
+        c.nodes[s - n_dense] = node;
+    }
+    return GLOP_OK;
+}
+
 }  // namespace
+
+uint32_t Compiled::step(uint32_t s, uint32_t k) const {
+    if (s < n_dense) return delta[(uint64_t)s * num_classes + k];
+    return glop_node_step(nodes.data(), in_edge.data(), n_dense, s, k);
+}
 
 // Filter stage: q-gram bitmap parameters and keys (Sections 2 and 5 filter
 // candidates by a short prefix before the full comparison).  Reads
@@ -165,7 +221,7 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             for (uint32_t g : keys) {
                 if (k == 3) {
                     const uint32_t h = glop_hash1(g);
-                    c.bitmap[glop_block_word(h, lg)] |= glop_block_bits(h);
+                    c.bitmap[glop_block_word(h, lg)] |= glop_block_bits(g);
                     continue;
                 }
                 const uint32_t s1 = glop_slot1(g, lg);
@@ -222,6 +278,10 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
     }
     if (n > 0 && (!patterns || !lengths)) {
         err = "NULL pattern or length array";
+        return GLOP_EINVAL;
+    }
+    if (o.layout > GLOP_LAYOUT_HYBRID || o.placement > GLOP_PLACE_LDS) {
+        err = "layout must be GLOP_LAYOUT_AUTO, _DENSE or _HYBRID and placement GLOP_PLACE_AUTO, _GLOBAL or _LDS";
         return GLOP_EINVAL;
     }
     if ((o.prefix_len > 255 && o.prefix_len != GLOP_PREFIX_FULL) ||
@@ -375,8 +435,14 @@ int compile(const uint8_t *const *patterns, const uint32_t *lengths, uint32_t n,
         }
 
         if (c.min_len >= 4) build_prefix_table(c, c.min_len >= 8 ? 8u : 4u);
-        const int rc = build_filter(patterns, n, o, c, err);
+        int rc = build_filter(patterns, n, o, c, err);
         if (rc != GLOP_OK) return rc;
+
+        // Device layout of the table.
+        c.layout = o.layout ? o.layout : (S * C * 4 > kAutoHybridBytes ? GLOP_LAYOUT_HYBRID : GLOP_LAYOUT_DENSE);
+        c.placement = o.placement;
+        c.n_dense = (uint32_t)S;
+        if (c.layout == GLOP_LAYOUT_HYBRID && (rc = build_hybrid(c, err)) != GLOP_OK) return rc;
     } catch (const std::bad_alloc &) {
         err = "host allocation failed while compiling the dictionary";
         return GLOP_ENOMEM;
@@ -391,10 +457,24 @@ struct Found {
     uint32_t state;
 };
 
-// Walk from every start in [lo, hi); record (start, deepest terminal).
+// Walk from every start in [lo, hi); record (start, deepest terminal).  A
+// hybrid table is walked in its device form (dense rows, then nodes).
 void walk_range(const Compiled &c, const uint8_t *text, uint64_t len, uint64_t lo, uint64_t hi,
                 std::vector<Found> &found) {
     const uint32_t C = c.num_classes;
+    if (c.layout == GLOP_LAYOUT_HYBRID) {
+        for (uint64_t i = lo; i < hi; ++i) {
+            uint32_t s = 0, last = 0;
+            for (uint64_t p = i; p < len; ++p) {
+                const uint32_t e = c.step(s, c.cls[text[p]]);
+                if (e == 0) break;
+                s = e & GLOP_STATE_MASK;
+                if (e & GLOP_TERM_BIT) last = s;
+            }
+            if (last) found.push_back({i, last});
+        }
+        return;
+    }
     for (uint64_t i = lo; i < hi; ++i) {
         uint32_t s = 0, last = 0;
         for (uint64_t p = i; p < len; ++p) {

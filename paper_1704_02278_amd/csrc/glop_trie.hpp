@@ -33,7 +33,21 @@ struct Compiled {
     // than 4 bytes; layout in glop_layout.hpp).
     std::vector<uint32_t> pt;  // 2^pt_lg slots of 4 words
     uint32_t pt_lg = 0, pt_probes = 0, pt_keys = 0, pt_depth = 0, pt_leaf = 0;
+    // Device layout of the transition table (glop_layout.hpp).  `delta` above
+    // always holds every row (the host walk and the prefix table use it); the
+    // device gets rows [0, n_dense) and, with the hybrid layout, one node per
+    // state from n_dense on and the edge byte of each of those states.
+    uint32_t layout = GLOP_LAYOUT_DENSE;
+    uint32_t placement = GLOP_PLACE_AUTO;  // as requested; resolved at upload
+    uint32_t n_dense = 1;
+    std::vector<uint64_t> nodes;    // hybrid: num_states - n_dense
+    std::vector<uint16_t> in_edge;  // hybrid: num_states - n_dense
     bool verifies() const { return prefix_len && !candidates; }
+    // The next state (with GLOP_TERM_BIT) or 0, read from the device layout.
+    uint32_t step(uint32_t s, uint32_t k) const;
+    uint64_t device_table_bytes() const {
+        return (uint64_t)n_dense * num_classes * 4 + nodes.size() * 8 + in_edge.size() * 2;
+    }
 };
 
 // Returns GLOP_OK or an error code with `err` set.

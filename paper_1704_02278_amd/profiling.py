@@ -1,11 +1,15 @@
 """rocprofv3 summaries for the matching kernels (run by path; reads CSV only).
 
     python paper_1704_02278_amd/profiling.py stats <..._kernel_stats.csv>
+    python paper_1704_02278_amd/profiling.py counters --text-bytes N [--kernel-us T] <..._counter_collection.csv> ...
     python paper_1704_02278_amd/profiling.py traffic --workload medium \\
         --fetch <fetch ..._counter_collection.csv> --write <write ..._counter_collection.csv> \\
         --out profiles/glop_scan_kernel_medium_traffic.json
 
 ``stats`` prints a markdown table of a ``--kernel-trace --stats`` run.
+``counters`` prints one kernel's counters from ``--pmc`` runs (SQ, TCC) with
+the ratios read from them: VALU instructions per tile and per byte, the VALU
+issue rate, LDS bank-conflict cycles per LDS instruction, the L2 hit rate.
 ``traffic`` turns two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE) of a
 program that also made one device copy of ``--copy-bytes`` bytes into HBM
 bytes per scan launch: each counter is scaled by what it reads for that copy.
@@ -99,6 +103,50 @@ def traffic(fetch_csv, write_csv, copy_bytes: int, kernel_prefix: str = "glop_sc
     return rec
 
 
+def counter_table(paths):
+    """{kernel short name: {counter: mean value per dispatch}} from --pmc CSVs."""
+    vals = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            vals.setdefault(k, {}).setdefault(r["Counter_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
+            # A counter collected per block instance sums over the instances of one dispatch.
+            vals[k][r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    return {k: {c: statistics.mean(d.values()) for c, d in cs.items()} for k, cs in vals.items()}
+
+
+def counters_report(paths, kernel_prefix, text_bytes, kernel_us=None, cus=256, clock_ghz=2.4):
+    """Markdown rows of raw counters and the ratios read from them for one kernel."""
+    tab = counter_table(paths)
+    ks = [k for k in tab if k.startswith(kernel_prefix)]
+    if len(ks) != 1:
+        raise ValueError(f"expected one {kernel_prefix} kernel in the counter runs, found {ks}")
+    c = tab[ks[0]]
+    out = [f"Kernel `{ks[0]}`, mean per dispatch:", "", "| counter | value |", "|---|---|"]
+    for name in sorted(c):
+        out.append(f"| {name} | {c[name]:,.0f} |")
+    out += ["", "| ratio | value |", "|---|---|"]
+    tiles = text_bytes / 8192.0
+    if "SQ_INSTS_VALU" in c:
+        out.append(f"| VALU wave instructions per 8 KiB tile | {c['SQ_INSTS_VALU'] / tiles:,.0f} |")
+        out.append(f"| VALU lane operations per text byte | {c['SQ_INSTS_VALU'] * 64 / text_bytes:.2f} |")
+        if kernel_us:
+            issue = c["SQ_INSTS_VALU"] / (cus * kernel_us * 1e-6 * clock_ghz * 1e9)
+            out.append(f"| VALU issue rate (wave instructions per CU per cycle; 1 is the CU's limit) | {issue:.3f} |")
+    if "SQ_INSTS_LDS" in c:
+        out.append(f"| LDS wave instructions per 8 KiB tile | {c['SQ_INSTS_LDS'] / tiles:,.0f} |")
+    if "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_INSTS_LDS"):
+        out.append(f"| LDS bank-conflict cycles per LDS instruction | "
+                   f"{c['SQ_LDS_BANK_CONFLICT'] / c['SQ_INSTS_LDS']:.3f} |")
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        tot = c["TCC_HIT_sum"] + c["TCC_MISS_sum"]
+        if tot:
+            out.append(f"| L2 (TCC) hit rate | {c['TCC_HIT_sum'] / tot:.4f} |")
+    if "SQ_INSTS_SALU" in c:
+        out.append(f"| SALU wave instructions per 8 KiB tile | {c['SQ_INSTS_SALU'] / tiles:,.0f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -110,9 +158,17 @@ def main(argv=None):
     t.add_argument("--write", required=True)
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--out")
+    c = sub.add_parser("counters")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("--kernel", default="glop_scan_kernel")
+    c.add_argument("--text-bytes", type=int, required=True)
+    c.add_argument("--kernel-us", type=float, help="the kernel's average duration (for the issue rate)")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv))
+        return 0
+    if a.cmd == "counters":
+        print(counters_report(a.csvs, a.kernel, a.text_bytes, a.kernel_us))
         return 0
     rec = traffic(a.fetch, a.write, a.copy_bytes)
     rec = {"workload": a.workload, **rec}

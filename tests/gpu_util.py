@@ -34,7 +34,27 @@ def variants_for(patterns):
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=3))
         if minlen >= 2:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=1, bitmap_log2=12))
+        # Table layouts and placements: dense rows to depth 2 and nodes below
+        # (for both engines), the dense rows read from device memory, and (when
+        # they fit beside the scan kernel's tables) from LDS.
+        out.append(dict(layout=glop.GLOP_LAYOUT_HYBRID))
+        if max(len(p) for p in patterns) > 8:
+            out.append(dict(layout=glop.GLOP_LAYOUT_HYBRID, prefix_len=glop.GLOP_PREFIX_FULL))
+        out.append(dict(placement=glop.GLOP_PLACE_GLOBAL))
+        out.append(dict(placement=glop.GLOP_PLACE_LDS, filter=glop.GLOP_FILTER_QGRAM, stride=1))
+        out.append(dict(placement=glop.GLOP_PLACE_LDS, layout=glop.GLOP_LAYOUT_HYBRID))
     return out
+
+
+def build_variant(patterns, opts):
+    """A device dictionary with `opts`, or None when the dictionary cannot take
+    them (dense rows placed in LDS that do not fit there)."""
+    try:
+        return glop.Dict(patterns, **opts)
+    except glop.GlopError as e:
+        if opts.get("placement") == glop.GLOP_PLACE_LDS and e.code == glop.GLOP_EINVAL:
+            return None
+        raise
 
 
 def to_device(text, shift: int = 0) -> torch.Tensor:

@@ -48,16 +48,51 @@ def test_hand_examples_through_compiled_trie():
         assert counts.tolist() == ex.counts and total == len(ex.matches)
 
 
-def test_random_small_cases_against_brute_force():
+@pytest.mark.parametrize("layout", [glop.GLOP_LAYOUT_DENSE, glop.GLOP_LAYOUT_HYBRID])
+def test_random_small_cases_against_brute_force(layout):
+    # Patterns up to 9 bytes over 1-3 letters: with the hybrid layout the trie
+    # goes well below its dense rows (depth <= 2), through states with one
+    # and with several children.
     rng = random.Random(99)
     for _ in range(200):
         alpha = b"abc"[: rng.randint(1, 3)]
-        pats = [bytes(rng.choice(alpha) for _ in range(rng.randint(1, 6))) for _ in range(rng.randint(1, 7))]
+        pats = [bytes(rng.choice(alpha) for _ in range(rng.randint(1, 9))) for _ in range(rng.randint(1, 7))]
         text = bytes(rng.choice(alpha) for _ in range(rng.randint(0, 200)))
         want, want_counts = brute_matches(text, pats)
-        off, ids, counts, total = host_dict(pats).cpu_walk(text, threads=rng.randint(1, 4))
+        d = host_dict(pats, layout=layout, prefix_len=glop.GLOP_PREFIX_FULL)
+        off, ids, counts, total = d.cpu_walk(text, threads=rng.randint(1, 4))
         assert list(zip(off.tolist(), ids.tolist())) == want
         assert counts.tolist() == want_counts and total == len(want)
+
+
+@pytest.mark.parametrize("name,n_bytes", [("tiny", None), ("medium", 2 << 20), ("large", 1 << 20)])
+def test_hybrid_layout_walks_like_the_dense_table(name, n_bytes):
+    """The hybrid layout, walked in its device form on the host (dense rows to
+    depth 2, then nodes), against the oracle; it is a small fraction of the
+    dense table and keeps every state."""
+    pats, text, _ = synth.make_workload(name, n_bytes=n_bytes)
+    o_off, o_ids, o_counts, o_total = oracle.match(text, pats, bucketed=2)
+    for prefix in (0, glop.GLOP_PREFIX_FULL):
+        dense = host_dict(pats, prefix_len=prefix, layout=glop.GLOP_LAYOUT_DENSE).info()
+        d = host_dict(pats, prefix_len=prefix, layout=glop.GLOP_LAYOUT_HYBRID)
+        info = d.info()
+        assert info["layout"] == glop.GLOP_LAYOUT_HYBRID and info["num_states"] == dense["num_states"]
+        assert 1 < info["dense_states"] < info["num_states"]
+        assert info["table_bytes"] < dense["table_bytes"] / 3
+        off, ids, counts, total = d.cpu_walk(text, threads=8)
+        assert total == o_total
+        assert np.array_equal(off, o_off.astype(np.uint64)) and np.array_equal(ids, o_ids.astype(np.uint64))
+        assert np.array_equal(counts, o_counts)
+
+
+def test_automatic_layout_is_hybrid_only_for_large_tables():
+    large, _, _ = synth.make_workload("large", n_bytes=1 << 16)
+    medium, _, _ = synth.make_workload("medium", n_bytes=1 << 16)
+    big = host_dict(large, prefix_len=glop.GLOP_PREFIX_FULL).info()  # 125 MB dense
+    assert big["layout"] == glop.GLOP_LAYOUT_HYBRID and big["table_bytes"] < 8e6
+    assert host_dict(large).info()["layout"] == glop.GLOP_LAYOUT_DENSE  # 8-byte prefixes: 30.5 MB
+    m = host_dict(medium).info()
+    assert m["layout"] == glop.GLOP_LAYOUT_DENSE and m["dense_states"] == m["num_states"]
 
 
 @pytest.mark.parametrize("name,n_bytes", [("tiny", None), ("medium", 2 << 20), ("large", 1 << 20)])
@@ -142,7 +177,7 @@ def test_build_errors():
                 dict(qgram=5, filter=glop.GLOP_FILTER_QGRAM),
                 dict(bitmap_log2=25, filter=glop.GLOP_FILTER_QGRAM),
                 dict(stride=4, filter=glop.GLOP_FILTER_NONE),
-                dict(filter=7)):
+                dict(filter=7), dict(layout=3), dict(placement=3)):
         with pytest.raises(glop.GlopError) as e:
             host_dict([b"abcd"], **bad)
         assert e.value.code == glop.GLOP_EINVAL

@@ -19,14 +19,16 @@ from golden_io import load_examples
 pytestmark = pytest.mark.gpu
 
 glop = pytest.importorskip("paper_1704_02278_amd")
-from gpu_util import assert_same, gpu_match, oracle_match, say, to_device, variants_for  # noqa: E402
+from gpu_util import assert_same, build_variant, gpu_match, oracle_match, say, to_device, variants_for  # noqa: E402
 
 
 def test_hand_examples_every_variant():
     for ex in load_examples():
         for opts in variants_for(ex.patterns):
             say("hand", ex.name, opts)
-            d = glop.Dict(ex.patterns, **opts)
+            d = build_variant(ex.patterns, opts)
+            if d is None:
+                continue
             off, ids, counts, total = gpu_match(d, to_device(ex.text))
             assert list(zip(off.tolist(), ids.tolist())) == ex.matches, (ex.name, opts)
             assert counts.tolist() == ex.counts and total == len(ex.matches), (ex.name, opts)
@@ -41,7 +43,10 @@ def test_random_small_cases_vs_brute_force():
         want, want_counts = brute_matches(text, pats)
         for opts in variants_for(pats):
             say("random", k, len(text), opts)
-            off, ids, counts, total = gpu_match(glop.Dict(pats, **opts), to_device(text, shift=k % 16))
+            d = build_variant(pats, opts)
+            if d is None:
+                continue
+            off, ids, counts, total = gpu_match(d, to_device(text, shift=k % 16))
             assert list(zip(off.tolist(), ids.tolist())) == want, (k, opts)
             assert counts.tolist() == want_counts and total == len(want), (k, opts)
 
@@ -54,7 +59,9 @@ def test_workload_parity(name, n_bytes):
     t = to_device(text)
     for opts in variants_for(pats):
         say("workload", name, text.size, opts)
-        assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"{name} {opts}")
+        d = build_variant(pats, opts)
+        if d is not None:
+            assert_same(gpu_match(d, t), want, f"{name} {opts}")
 
 
 def test_unaligned_text_and_ragged_lengths():
@@ -83,7 +90,9 @@ def test_tile_boundary_straddles():
     for shift in (0, 5, 13):
         for opts in variants_for(pats):
             say("straddle", shift, opts)
-            assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text, shift=shift)), want, f"{opts}")
+            d = build_variant(pats, opts)
+            if d is not None:
+                assert_same(gpu_match(d, to_device(text, shift=shift)), want, f"{opts}")
 
 
 def test_dense_matches_take_the_overflow_path():
@@ -92,7 +101,9 @@ def test_dense_matches_take_the_overflow_path():
     want = oracle_match(text, pats)
     for opts in variants_for(pats):
         say("dense", opts)
-        assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text)), want, f"dense {opts}")
+        d = build_variant(pats, opts)
+        if d is not None:
+            assert_same(gpu_match(d, to_device(text)), want, f"dense {opts}")
 
 
 def test_truncation_keeps_sorted_prefix_and_full_counts():
@@ -128,7 +139,9 @@ def test_binary_bytes():
     want = oracle_match(text, pats)
     for opts in variants_for(pats):
         say("binary", opts)
-        assert_same(gpu_match(glop.Dict(pats, **opts), to_device(text, shift=3)), want, f"binary {opts}")
+        d = build_variant(pats, opts)
+        if d is not None:
+            assert_same(gpu_match(d, to_device(text, shift=3)), want, f"binary {opts}")
 
 
 def test_repeated_runs_are_identical():
@@ -189,7 +202,9 @@ def test_prefix_table_on_both_sides_of_the_lds_limit(n_pats, lo, hi):
     t = to_device(text, shift=5)
     for opts in variants_for(pats):
         say("prefix-table", n_pats, opts)
-        assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"prefix table {n_pats} {opts}")
+        d = build_variant(pats, opts)
+        if d is not None:
+            assert_same(gpu_match(d, t), want, f"prefix table {n_pats} {opts}")
 
 
 def test_item_count_flips_with_the_text_alignment():
@@ -237,3 +252,38 @@ def test_total_written_to_pinned_host_memory():
         torch.cuda.synchronize()
         assert int(host_total[0]) == want[3]
     assert np.array_equal(out[:want[3], 0].cpu().numpy().astype(np.uint64), want[0])
+
+
+def test_table_layouts_and_placements_on_the_large_dictionary():
+    """The whole-pattern trie of the large dictionary (325,458 states): the
+    automatic layout is hybrid (about 6 MB instead of 125 MB), and dense, hybrid
+    and (where it fits) LDS-placed rows all give the oracle's result; dense
+    rows that cannot fit in LDS are refused at build."""
+    pats, text, _ = synth.make_workload("large", n_bytes=6 << 20)
+    want = oracle_match(text, pats, bucketed=2)
+    t = to_device(text, shift=7)
+    full = glop.GLOP_PREFIX_FULL
+    auto = glop.Dict(pats, prefix_len=full)
+    assert auto.info()["layout"] == glop.GLOP_LAYOUT_HYBRID and auto.info()["table_bytes"] < 8e6
+    for opts in (dict(prefix_len=full), dict(prefix_len=full, layout=glop.GLOP_LAYOUT_DENSE),
+                 dict(layout=glop.GLOP_LAYOUT_HYBRID), dict(layout=glop.GLOP_LAYOUT_HYBRID, filter=glop.GLOP_FILTER_NONE)):
+        say("layout", opts)
+        assert_same(gpu_match(glop.Dict(pats, **opts), t), want, f"large {opts}")
+    with pytest.raises(glop.GlopError) as e:
+        glop.Dict(pats, prefix_len=full, placement=glop.GLOP_PLACE_LDS)
+    assert e.value.code == glop.GLOP_EINVAL
+
+
+def test_lds_placed_rows_on_the_tiny_dictionary():
+    pats, text, _ = synth.make_workload("tiny")
+    want = oracle_match(text, pats)
+    t = to_device(text, shift=1)
+    auto = glop.Dict(pats, prefix_len=glop.GLOP_PREFIX_FULL)
+    assert auto.info()["placement"] == glop.GLOP_PLACE_LDS  # a few KB of rows fit beside the filter
+    for opts in (dict(prefix_len=glop.GLOP_PREFIX_FULL), dict(placement=glop.GLOP_PLACE_GLOBAL),
+                 dict(placement=glop.GLOP_PLACE_LDS, layout=glop.GLOP_LAYOUT_HYBRID),
+                 dict(placement=glop.GLOP_PLACE_LDS, filter=glop.GLOP_FILTER_NONE)):
+        say("placement", opts)
+        d = glop.Dict(pats, **opts)
+        assert d.info()["placement"] == opts.get("placement", glop.GLOP_PLACE_LDS)
+        assert_same(gpu_match(d, t), want, f"tiny {opts}")
