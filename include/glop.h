@@ -45,7 +45,7 @@ extern "C" {
 #define GLOP_EINVAL (-1)   /* invalid argument (NULL pointer, empty pattern, bad option, small workspace) */
 #define GLOP_ENOMEM (-2)   /* host or device allocation failed, or the dictionary is too large */
 #define GLOP_EHIP (-3)     /* a HIP runtime call failed (message names it) */
-#define GLOP_ETOOLONG (-4) /* a pattern is longer than GLOP_MAX_PATTERN_LEN */
+#define GLOP_ETOOLONG (-4) /* a pattern is longer than GLOP_MAX_PATTERN_LEN, or a text too long for glop_match_static */
 #define GLOP_ENODEV (-5)   /* no usable GPU, or the handle has no device copy */
 #define GLOP_EINTERNAL (-6) /* an internal consistency check failed */
 
@@ -269,6 +269,30 @@ typedef struct {
 int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
                   uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, void *d_workspace,
                   uint64_t workspace_bytes, void *stream, const glop_events_t *events);
+
+/*
+ * For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, hosts that forbid allocation): glop_match_ws
+ * with the library's own workspace, a static device array of 32 MiB that each
+ * device holds from the library's first use on it until the process ends.
+ * Allocates nothing.
+ *
+ *   d_total      as in glop_match_ws (may be NULL).
+ *   other arguments as glop_match.
+ *
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (two streams, or two host threads) race and give wrong results.
+ * Serialise them, or use glop_match_ws with a workspace per stream.  The
+ * kernels write every workspace word they later read, so nothing needs
+ * clearing between calls.  A text whose workspace would exceed the array
+ * (glop_static_max_len(h) bytes or more, about 1.8 GiB on 256 CUs) gives
+ * GLOP_ETOOLONG before anything is enqueued.  Other errors as glop_match_ws.
+ */
+int glop_match_static(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
+                      uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, void *stream);
+
+/* Longest text glop_match_static accepts for this handle's device (0 for NULL). */
+uint64_t glop_static_max_len(glop_handle_t h);
 
 /*
  * Batches: many independent texts ("chunks", e.g. log files of uneven size)

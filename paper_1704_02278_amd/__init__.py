@@ -120,6 +120,8 @@ _SIGNATURES = {
     "glop_match_ws": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _vp,
                                      ctypes.POINTER(glop_events_t)]),
     "glop_match_host": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _u64, _vp]),
+    "glop_match_static": (ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
+    "glop_static_max_len": (_u64, [_vp]),
     "glop_batch_workspace_bytes": (_u64, [_vp, ctypes.c_uint32, _u64]),
     "glop_match_batch": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u64, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64,
                                         _vp]),

@@ -70,6 +70,11 @@ int upload(glop_dict *h) {
         if (dev >= 0 && dev < 64 && !g_prepared[dev]) {
             e = glop::prepare_kernels();
             if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute");
+            // The device address of the static workspace (glop_match_static),
+            // looked up once per device while it is current.
+            void *ws = nullptr;
+            e = glop::static_scratch(dev, &ws);
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static workspace");
             g_prepared[dev] = true;
         }
     }
@@ -636,6 +641,37 @@ int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_mat
     hipError_t e = glop::launch_match(a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return ok();
+}
+
+uint64_t glop_static_max_len(glop_handle_t h) {
+    if (!h) return 0;
+    // Workspace bytes grow with the length; the largest length that fits.
+    uint64_t lo = 0, hi = 1ull << 40;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (glop::workspace_bytes(mid, h->num_cus) <= glop::kStaticScratchBytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int glop_match_static(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
+                      uint64_t max_matches, uint64_t *d_counts, uint64_t *d_total, void *stream) {
+    int rc = check_match_args(h, d_text, len, d_out, max_matches, d_counts);
+    if (rc != GLOP_OK) return rc;
+    rc = check_device(h);
+    if (rc != GLOP_OK) return rc;
+    const uint64_t need = glop::workspace_bytes(len, h->num_cus);
+    if (need > glop::kStaticScratchBytes)
+        return fail(GLOP_ETOOLONG, "text of " + std::to_string(len) + " bytes needs " + std::to_string(need) +
+                                       " bytes of workspace; the static workspace holds " +
+                                       std::to_string(glop::kStaticScratchBytes) + " (at most " +
+                                       std::to_string(glop_static_max_len(h)) + " bytes of text)");
+    void *ws = nullptr;
+    const hipError_t e = glop::static_scratch(h->device, &ws);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the static workspace");
+    return glop_match_ws(h, d_text, len, d_out, max_matches, d_counts, d_total, ws, glop::kStaticScratchBytes, stream,
+                         nullptr);
 }
 
 int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,

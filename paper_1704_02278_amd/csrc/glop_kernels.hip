@@ -2,6 +2,8 @@
 // dictionary and enqueues a single-text match or a batch.
 #include "glop_kernels_impl.hpp"
 
+#include <mutex>
+
 namespace glop {
 namespace detail {
 
@@ -98,6 +100,27 @@ ScanParams base_params(const GlopDevDict &d, uint64_t *counts) {
 }  // namespace detail
 
 using namespace detail;
+
+// Workspace for callers that cannot allocate: one array per device, held from
+// the library's load until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory: every use goes through the
+// device address that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(int device, void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus, kMinTileBytes, 15).bytes; }
 

@@ -47,6 +47,13 @@ struct BatchLaunch {
 // Device workspace needed for a text of `len` bytes (any alignment).
 uint64_t workspace_bytes(uint64_t len, int num_cus);
 
+// The library's own workspace for callers that cannot allocate: a static
+// device array of kStaticScratchBytes per device.  static_scratch() gives its
+// address on `device`, which must be the current device (looked up on the
+// first call, then cached).
+constexpr uint64_t kStaticScratchBytes = 32ull << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int device, void **ptr);
 
 // Device workspace needed for a batch of nchunks chunks, max_total_bytes in all.
 uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes);
