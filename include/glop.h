@@ -83,12 +83,16 @@ typedef struct glop_dict *glop_handle_t;
  *               the shortest pattern length.
  *   bitmap_log2 0 = automatic; else 12..19 (filter bitmap of 2^bitmap_log2 bits,
  *               resident in LDS).
- *   probe_bits  0 = automatic (3 at stride 1, where the probes' LDS reads
- *               dominate; 2 at stride 4, where the walks of false positives
- *               do); 1 or 2 bits per q-gram at independent
- *               positions (a Bloom filter with one or two hash functions), or
- *               3 = two bits within one 32-bit word chosen by one hash (a
- *               blocked Bloom filter: one lookup per probe).
+ *   probe_bits  0 = automatic (3 at stride 1, where every offset is probed
+ *               and the probes' LDS reads dominate; 2 at stride 4, where the
+ *               walks of false positives do);
+ *               1 or 2 bits per q-gram at independent positions (a Bloom
+ *               filter with one or two hash functions); 3 = two bits within
+ *               one 32-bit word chosen by one hash (a blocked Bloom filter:
+ *               one lookup per probe); 4 = two bits within one 16-bit block
+ *               (stride 1, 4-byte q-grams, bitmap_log2 19 only), which lets
+ *               the kernel probe two offsets per instruction on packed
+ *               16-bit halves.
  *   tile_kib    0 = automatic, or 8: KiB of text one wavefront streams per
  *               tile (16 bytes per lane per round, 8 rounds).
  *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;

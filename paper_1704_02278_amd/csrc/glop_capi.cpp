@@ -559,7 +559,7 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
         const uint32_t pb0 = cur.probe_bits;
-        for (uint32_t pb = 1; pb <= 3; ++pb) {
+        for (uint32_t pb = 1; pb <= 4; ++pb) {
             if (pb == pb0) continue;
             glop_build_opts cand = cur;
             cand.probe_bits = pb;

@@ -16,6 +16,7 @@ GLOP_DECLARE_VARIANT(4, 1, 1, 0, 8)
 GLOP_DECLARE_VARIANT(4, 1, 1, 1, 8)
 GLOP_DECLARE_VARIANT(4, 1, 2, 0, 8)
 GLOP_DECLARE_VARIANT(4, 1, 2, 1, 8)
+GLOP_DECLARE_VARIANT(1, 1, 4, 1, 8)
 GLOP_DECLARE_VARIANT(1, 1, 3, 0, 8)
 GLOP_DECLARE_VARIANT(1, 1, 3, 1, 8)
 GLOP_DECLARE_VARIANT(4, 1, 3, 0, 8)
@@ -27,6 +28,7 @@ namespace {
 const VariantFns &variant_for(const GlopDevDict &d) {
     if (d.filter != GLOP_FILTER_QGRAM) return GLOP_VARIANT_ID(1, 0, 1, 0, 8)();
     const bool q4 = d.qgram == 4, k2 = d.probe_bits == 2;
+    if (d.probe_bits == 4) return GLOP_VARIANT_ID(1, 1, 4, 1, 8)();  // stride 1, 4-byte q-grams (checked at build)
     if (d.probe_bits == 3) {
         if (d.stride == 4) return q4 ? GLOP_VARIANT_ID(4, 1, 3, 1, 8)() : GLOP_VARIANT_ID(4, 1, 3, 0, 8)();
         return q4 ? GLOP_VARIANT_ID(1, 1, 3, 1, 8)() : GLOP_VARIANT_ID(1, 1, 3, 0, 8)();
@@ -152,7 +154,7 @@ hipError_t prepare_kernels() {
                                &GLOP_VARIANT_ID(4, 1, 1, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 2, 0, 8)(),
                                &GLOP_VARIANT_ID(4, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(1, 1, 3, 0, 8)(),
                                &GLOP_VARIANT_ID(1, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(4, 1, 3, 0, 8)(),
-                               &GLOP_VARIANT_ID(4, 1, 3, 1, 8)()};
+                               &GLOP_VARIANT_ID(4, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(1, 1, 4, 1, 8)()};
     for (const VariantFns *v : all) {
         const hipError_t e = v->set_lds_limit();
         if (e != hipSuccess) return e;

@@ -116,9 +116,16 @@ static_assert((1u << GLOP_FILTER2_LOG2) / 8 <= pt_lds_cap<1>(), "second filter e
 template <bool BATCH>
 constexpr uint32_t item_tiles_cap() { return BATCH ? kMaxBatchTilesPerItem : kMaxTilesPerItem; }
 
-// Dynamic LDS the scan kernels may use (the workgroup's 160 KiB less room for
-// their few static words).
+// Dynamic LDS the scan kernels may use (of the workgroup's 160 KiB).
 constexpr uint32_t kScanLdsLimit = 160u * 1024u - 1024u;
+
+// The scan kernel's shared words (in dynamic LDS, after its tables).
+struct ScanShared {
+    uint32_t hl_count, item_failed, tile_next, hl_walked;
+    uint64_t item_sh;
+    uint64_t red[16];
+};
+constexpr uint32_t kScanSharedBytes = (sizeof(ScanShared) + 15u) & ~15u;
 
 // Dynamic LDS: bitmap | byte classes | per-wave rings | hit list (stride 4) |
 // per-tile matched-start counts | per-tile record counts | prefix table or
@@ -138,7 +145,11 @@ struct LdsLayout {
     __host__ __device__ constexpr uint32_t pt_off() const { return rec_off() + item_tiles_cap<BATCH>() * 8; }
     __host__ __device__ constexpr uint32_t f2_off() const { return pt_off() + pt_bytes; }
     __host__ __device__ constexpr uint32_t tab_off() const { return f2_off() + f2_bytes; }
-    __host__ __device__ constexpr uint32_t bytes() const { return tab_off() + tab_bytes; }
+    // The scan kernel's few shared words come last, so that its LDS tables
+    // start at address 0 (a table address is then its index, with no base
+    // to add).
+    __host__ __device__ constexpr uint32_t sh_off() const { return (tab_off() + tab_bytes + 15u) & ~15u; }
+    __host__ __device__ constexpr uint32_t bytes() const { return sh_off() + kScanSharedBytes; }
 };
 
 // A text as the kernels see it: coordinates x count bytes from abase, the
@@ -1045,8 +1056,8 @@ __device__ __forceinline__ void filter2_batch(const Stage2 &st, const uint32_t *
 
 template <int R, bool FILTER, int K, bool Q4>
 __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo &ti, const TileRegs<R> &r,
-                                            const uint32_t *bm, const uint32_t *bm2, uint32_t (&m)[R / 2],
-                                            const Stage2 *st = nullptr) {
+                                            const uint32_t *bm, uint32_t bm_addr, const uint32_t *bm2,
+                                            uint32_t (&m)[R / 2], const Stage2 *st = nullptr) {
     static_assert(R / 2 <= 4, "reject words hold four round pairs");
     const uint32_t lane = lane_id();
     const uint32_t qmask = d.qmask, sh = 32u - d.bitmap_log2;
@@ -1079,16 +1090,56 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
             auto key = [&](int u) -> uint32_t {
                 return (u & 3) ? __builtin_amdgcn_alignbyte(w[(u >> 2) + 1], w[u >> 2], u & 3) : w[u >> 2];
             };
+            if constexpr (K == 4) {
+                // Paired probes (glop_layout.hpp): offsets u and u + 2 in the
+                // two 16-bit halves.  The word at u holds the low halves of
+                // both keys and the first bytes' shift amounts, the word at
+                // u + 2 the high halves, the word at u + 1 the second bytes'
+                // shift amounts.  Pair (u, u + 2) sets bits u and u + 16 of
+                // a1, and bit 16 + u lands on offset u + 2 below.
+                typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+                const us2 hA = {(unsigned short)GLOP_HASH16_A, (unsigned short)GLOP_HASH16_A};
+                const us2 hB = {(unsigned short)GLOP_HASH16_B, (unsigned short)GLOP_HASH16_B};
+                // A block's byte address is the masked hash plus the filter's
+                // LDS address bm_addr: 0 in the scan kernel, whose tables start
+                // at LDS address 0 (the build checks that it has no static
+                // LDS), so there the sum is the masked hash itself.
+                typedef __attribute__((address_space(3))) const unsigned short lds_u16;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                probe_acc<K, Q4>(bm, key(u), key(u + 1), qmask, sh, a1, a2);
-                if ((u & 3) == 3) {
-                    // Finish these probes here (see tile_hits4).
-                    __asm__ volatile("" : "+v"(a1), "+v"(a2));
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int v = 0; v < 8; ++v) {
+                    const int u = (v & 1) + 4 * (v >> 1);  // 0, 1, 4, 5, 8, 9, 12, 13
+                    const uint32_t xu = key(u), xu1 = key(u + 1), xu2 = key(u + 2);
+                    const us2 h = __builtin_bit_cast(us2, xu) * hA + __builtin_bit_cast(us2, xu2) * hB;
+                    const uint32_t hh = __builtin_bit_cast(uint32_t, h);
+                    const us2 wb = {*(lds_u16 *)(size_t)(bm_addr + (hh & 0xFFFEu)),
+                                    *(lds_u16 *)(size_t)(bm_addr + ((hh >> 16) & 0xFFFEu))};
+                    // Each half shifted by the low four bits of its own byte
+                    // (v_pk_lshrrev_b16 reads only those, so the keys need no
+                    // mask; written out because C shifts by 16 or more are
+                    // undefined).
+                    uint32_t s1, s2;
+                    const uint32_t wr = __builtin_bit_cast(uint32_t, wb);
+                    __asm__("v_pk_lshrrev_b16 %0, %1, %2" : "=v"(s1) : "v"(xu), "v"(wr));
+                    __asm__("v_pk_lshrrev_b16 %0, %1, %2" : "=v"(s2) : "v"(xu1), "v"(wr));
+                    a1 = ((s1 & s2 & 0x00010001u) << u) | a1;
+                    if ((v & 1) == 1) {
+                        __asm__ volatile("" : "+v"(a1));
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
+                mask = (a1 | (a1 >> 14)) & 0xFFFFu;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    probe_acc<K, Q4>(bm, key(u), key(u + 1), qmask, sh, a1, a2);
+                    if ((u & 3) == 3) {
+                        // Finish these probes here (see tile_hits4).
+                        __asm__ volatile("" : "+v"(a1), "+v"(a2));
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                mask = (a1 & a2) >> 16;
             }
-            mask = (a1 & a2) >> 16;
             if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
             if (f2) {
                 // Stage the survivors' keys: each pass adds every lane's next
@@ -1192,7 +1243,8 @@ __device__ __forceinline__ void scan_loaded_tile(const ScanParams &P, uint64_t t
         walk_hits4<R>(P, t, ti, pbits, xb, tabs, queue, sink);
     } else {
         uint32_t m[R / 2];
-        tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, nullptr, m);
+        typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+        tile_masks1<R, FILTER, K, Q4>(P.d, ti, r, bm, (uint32_t)(size_t)(lds_u32 *)bm, nullptr, m);
         walk_offsets1<R>(P, t, ti, m, tabs, queue, sink);
     }
 }
@@ -1237,10 +1289,13 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     constexpr int TILE = R * kRoundBytes;
     constexpr bool kDefer = FILTER;  // deferred walks through the workgroup list (every filtered variant)
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t hl_count, item_failed, tile_next, hl_walked;
-    __shared__ uint64_t item_sh;
-    __shared__ uint64_t red[kWaves];
     const LdsLayout<STRIDE, BATCH> Lo{P.bm_bytes, P.pt_lds_bytes, P.f2_lds_bytes, P.tab_lds_bytes};
+    ScanShared &sh = *reinterpret_cast<ScanShared *>(lds + Lo.sh_off());
+    uint32_t &hl_count = sh.hl_count, &item_failed = sh.item_failed, &tile_next = sh.tile_next,
+             &hl_walked = sh.hl_walked;
+    uint64_t &item_sh = sh.item_sh;
+    uint64_t *red = sh.red;
+    static_assert(sizeof(ScanShared::red) == kWaves * sizeof(uint64_t), "one reduction word per wave");
     uint32_t *bm = reinterpret_cast<uint32_t *>(lds);
     uint8_t *cls = lds + Lo.cls_off();
     const uint32_t wave = wave_id();
@@ -1345,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 uint32_t m[R / 2];
                 const Stage2 st2{reinterpret_cast<uint2 *>(queue),
                                  reinterpret_cast<uint32_t *>(queue) + 2 * Stage2::kEntries};
-                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, bm2, m, &st2);
+                tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, 0u, bm2, m, &st2);  // bm: LDS address 0
                 if (has_next) load_tile<R, FILTER>(nxt, r);
                 // Survivors wait in the workgroup list, so walks run in full
                 // batches of 64 instead of one short batch per tile.  Here the

@@ -1,5 +1,5 @@
-"""Check the gfx950 assembly of the kernels for barriers in divergent loops
-and for scratch use.
+"""Check the gfx950 assembly of the kernels for barriers in divergent loops,
+for scratch use, and for static LDS in the scan kernels.
 
 A workgroup barrier (s_barrier) is counted per wave: a wave arrives when its
 active lanes reach it.  If the compiler gives a loop that holds a barrier a
@@ -114,6 +114,24 @@ def check_function(body):
 
 _KD = re.compile(r"^\s*\.amdhsa_kernel\s+(\S+)")
 _PRIVATE = re.compile(r"^\s*\.amdhsa_private_segment_fixed_size\s+(\d+)")
+_GROUP = re.compile(r"^\s*\.amdhsa_group_segment_fixed_size\s+(\d+)")
+# Kernels whose LDS tables must start at address 0 (no static LDS): the scan
+# kernels address their filter blocks by the masked hash alone.
+_NO_STATIC_LDS = "glop_scan_kernel"
+
+
+def group_sizes(lines):
+    """Static LDS bytes of every kernel, from its kernel descriptor."""
+    out, name = {}, None
+    for line in lines:
+        m = _KD.match(line)
+        if m:
+            name = m.group(1)
+            continue
+        m = _GROUP.match(line)
+        if m and name is not None:
+            out[name] = int(m.group(1))
+    return out
 
 
 def scratch_sizes(lines):
@@ -147,6 +165,9 @@ def check_file(path):
     for name, size in scratch_sizes(lines).items():
         if size > 0:
             out.setdefault(name, []).append(f"uses {size} bytes of scratch per lane (register spill)")
+    for name, size in group_sizes(lines).items():
+        if _NO_STATIC_LDS in name and size > 0:
+            out.setdefault(name, []).append(f"has {size} bytes of static LDS (its tables must start at address 0)")
     return out
 
 

@@ -28,6 +28,8 @@ def variants_for(patterns):
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=1))
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=3))
+        if minlen >= 4:
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=4))
         if minlen >= 7:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=1))
@@ -68,11 +70,32 @@ def to_device(text, shift: int = 0) -> torch.Tensor:
     return t
 
 
+SENTINEL = -0x0123456789ABCDEF
+
+
 def gpu_match(d: glop.Dict, text_dev: torch.Tensor, max_matches=None):
-    off, ids, counts, total = d.match(text_dev, max_matches=max_matches)
-    torch.cuda.synchronize()
-    return (off.cpu().numpy().astype(np.uint64), ids.cpu().numpy().astype(np.uint64),
-            counts.cpu().numpy().astype(np.uint64), int(total))
+    """Match through glop_match_ws into outputs pre-filled with a sentinel, so a
+    record the kernels fail to write cannot pass as one left behind by an
+    earlier call in the same memory; the first pass sizes the output."""
+    n = int(text_dev.numel())
+    dev = text_dev.device
+    ws = torch.empty(d.workspace_bytes(n) + 256, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:]
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = max(1024, n // 1024) if max_matches is None else int(max_matches)
+    while True:
+        out = torch.full((max(cap, 1), 2), SENTINEL, dtype=torch.int64, device=dev)
+        counts = torch.full((max(1, d.num_patterns),), SENTINEL, dtype=torch.int64, device=dev)
+        d.match_into(text_dev, out, counts, max_matches=cap, total=total, workspace=ws)
+        got = int(total.item())
+        if max_matches is not None or got <= cap:
+            break
+        cap = got
+    k = min(cap, got)
+    o = out[:k].cpu().numpy()
+    assert np.all(out[k:].cpu().numpy() == SENTINEL), "a record was written past the total"
+    return (o[:, 0].astype(np.uint64), o[:, 1].astype(np.uint64),  # the id with its zero reserved word
+            counts[: d.num_patterns].cpu().numpy().astype(np.uint64), got)
 
 
 def oracle_match(text, patterns, threads=None, bucketed=1):

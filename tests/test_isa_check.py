@@ -92,10 +92,10 @@ def test_divergent_loop_without_barrier_is_fine(tmp_path):
     assert _check(GOOD.replace("\ts_barrier\n", ""), tmp_path) == {}
 
 
-def _descriptor(name, scratch):
+def _descriptor(name, scratch, group=160):
     return f"""\
 	.amdhsa_kernel {name}
-		.amdhsa_group_segment_fixed_size 160
+		.amdhsa_group_segment_fixed_size {group}
 		.amdhsa_private_segment_fixed_size {scratch}
 		.amdhsa_kernarg_size 304
 	.end_amdhsa_kernel
@@ -111,3 +111,12 @@ def test_scratch_sizes_read_from_every_descriptor(tmp_path):
     f = tmp_path / "k.s"
     f.write_text(_descriptor("a", 0) + _descriptor("b", 8) + _descriptor("c", 0))
     assert isa_check.scratch_sizes(f.read_text().splitlines()) == {"a": 0, "b": 8, "c": 0}
+
+
+def test_scan_kernels_must_have_no_static_lds(tmp_path):
+    scan = "_ZN4glop6detail16glop_scan_kernelILi1ELb1ELi4ELb1ELi8ELb0EEEvNS0_10ScanParamsE"
+    emit = "_ZN4glop6detail16glop_emit_kernelILi1ELb1ELi4ELb1ELi8ELb0EEEvNS0_10ScanParamsENS0_10EmitParamsE"
+    ok = _check(_descriptor(scan, 0, group=0) + _descriptor(emit, 0, group=37000), tmp_path)
+    assert ok == {}
+    bad = _check(_descriptor(scan, 0, group=16), tmp_path)
+    assert bad == {scan: ["has 16 bytes of static LDS (its tables must start at address 0)"]}
