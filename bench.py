@@ -374,6 +374,10 @@ def main() -> int:
     ap.add_argument("--no-host-stream", action="store_true", help="skip the host-streamed input measurement")
     ap.add_argument("--no-alt", action="store_true", help="skip the alternative engine/filter configurations")
     ap.add_argument("--served-requests", type=int, default=20000)
+    ap.add_argument("--prefix-len", default="auto",
+                    help="trie depth of the timed dictionary: auto (the library's default), full, or a byte count")
+    ap.add_argument("--layout", default="auto", choices=["auto", "dense", "hybrid"],
+                    help="transition-table layout of the timed dictionary")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the matcher has no multi-GPU path",
@@ -391,7 +395,12 @@ def main() -> int:
         f"generated in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    d = glop.Dict(pats)
+    dict_opts = {}
+    if args.prefix_len != "auto":
+        dict_opts["prefix_len"] = glop.GLOP_PREFIX_FULL if args.prefix_len == "full" else int(args.prefix_len)
+    if args.layout != "auto":
+        dict_opts["layout"] = {"dense": glop.GLOP_LAYOUT_DENSE, "hybrid": glop.GLOP_LAYOUT_HYBRID}[args.layout]
+    d = glop.Dict(pats, **dict_opts)
     info = d.info()
     log(f"[bench] dictionary: {info}")
     t_dev = torch.from_numpy(text).to(dev)
@@ -513,7 +522,9 @@ def main() -> int:
         "dtype": "u8",
         "data": "synthetic (seeded MT19937-64 log lines and patterns, planted occurrences)",
         "config": {"workload": WORKLOAD_LABEL[args.workload], "patterns": len(pats), "text_bytes": n,
-                   "form": "plain (one glop_match_ws call per step)"},
+                   "form": "plain (one glop_match_ws call per step)",
+                   **({"dictionary_options": {"prefix_len": args.prefix_len, "layout": args.layout}}
+                      if dict_opts else {})},
         "sha256": {"text": synth.sha256_bytes(text), "patterns": synth.sha256_patterns(pats)},
         "gbps_eq1": round(8 * value, 2),
         "hbm_frac": round(value / HBM_PEAK_GBS, 5),
@@ -522,7 +533,7 @@ def main() -> int:
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "matches": got_total,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(args.workload),
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None if dict_opts else measured_traffic(args.workload),
                      "kernel": "glop_scan_kernel", "kernel_ms_avg": round(scan_avg, 5),
                      "kernel_event_samples": int(scan_ms.size),
                      "algorithmic_bytes_per_launch": int(scan_bytes)},

@@ -202,11 +202,9 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.nchunks = a.nchunks;
     P.tile_cap = g.tile_cap;
     P.item_cap = g.item_cap;
-    // Items small enough that every CU gets work, one tile per wave at least.
-    const uint64_t cus = (uint64_t)(a.num_cus > 0 ? a.num_cus : 1);
-    uint64_t per = (g.tile_cap + cus - 1) / cus;
-    per = per < kMinBatchTilesPerItem ? kMinBatchTilesPerItem : (per > kMaxBatchTilesPerItem ? kMaxBatchTilesPerItem : per);
-    P.tiles_per_item = per;
+    // The prep kernel sizes the work items once it knows the tile count
+    // (kMetaPer); this is only their upper bound.
+    P.tiles_per_item = kMaxBatchTilesPerItem;
     uint8_t *ws = static_cast<uint8_t *>(a.workspace);
     P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);
     P.tile_nm = reinterpret_cast<uint32_t *>(ws + g.off_nm);

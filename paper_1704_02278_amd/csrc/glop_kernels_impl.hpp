@@ -88,7 +88,10 @@ __host__ __device__ constexpr uint64_t single_tiles_per_item(uint64_t ntiles, ui
 }
 
 // Batch metadata words in the workspace.
-enum { kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaError = 5, kMetaWords = 8 };
+enum {
+    kMetaTiles = 0, kMetaItems = 1, kMetaTicket = 2, kMetaOverflow = 3, kMetaTotal = 4, kMetaError = 5, kMetaPer = 6,
+    kMetaWords = 8
+};
 
 // A listed hit word is written right after its space is reserved; a walker
 // waits for it at most this many short sleeps (about 0.1 s) before giving up
@@ -273,6 +276,19 @@ __device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t &tota
     return pre;
 }
 
+// Workgroup barrier that first waits until this wave's own LDS operations,
+// atomics included, have completed, so that every wave reads their results
+// after it.  The compiler's barrier alone leaves out that wait on some paths
+// (where a loop that ends in an LDS atomic add exits straight into the
+// barrier): a per-tile record count read after it then missed the last add of
+// another wave's walk batch now and then, and the call reported too few
+// matches.  lgkmcnt(0), vmcnt and expcnt unconstrained: 0xC07F in the gfx9
+// s_waitcnt encoding.
+__device__ __forceinline__ void wg_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __syncthreads();
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -289,7 +305,7 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
         if (lane >= (uint32_t)o) incl += y;
     }
     if (lane == kWave - 1) sh[wave] = incl;
-    __syncthreads();
+    wg_barrier();
     if (wave == 0) {
         const uint64_t w = lane < kWaves ? sh[lane] : 0ull;
         uint64_t wi = w;
@@ -301,10 +317,10 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *sh
         if (lane < kWaves) sh[lane] = wi - w;
         if (lane == kWaves - 1) sh[kWaves] = wi;
     }
-    __syncthreads();
+    wg_barrier();
     const uint64_t excl = sh[wave] + incl - v;
     total = sh[kWaves];
-    __syncthreads();
+    wg_barrier();
     return excl;
 }
 
@@ -314,10 +330,10 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (lane == 0) sh[wave] = v;
-    __syncthreads();
+    wg_barrier();
     uint64_t s = 0;
     for (int w = 0; w < kWaves; ++w) s += sh[w];
-    __syncthreads();
+    wg_barrier();
     return s;
 }
 
@@ -1142,15 +1158,17 @@ __device__ __forceinline__ void tile_masks1(const GlopDevDict &d, const TileInfo
             }
             if (!full) mask &= valid_mask16(ti.s, ti.x0 + (uint64_t)k * kRoundBytes + lane * 16u);
             if (f2) {
-                // Stage the survivors' keys: each pass adds every lane's next
-                // survivor; 64 waiting entries are checked at once.
-                uint32_t left = mask;
-                for (;;) {
-                    const uint64_t bal = __ballot(left != 0u);
-                    if (bal == 0) break;
-                    if (left) {
-                        const uint32_t u = (uint32_t)__builtin_ctz(left);
-                        left &= left - 1u;
+                // Stage each lane's first survivor of the round; 64 waiting
+                // entries are checked at once.  A lane's further survivors
+                // in the round (about one lane-round in 170 has one) skip
+                // the second filter: it only removes offsets, so an offset
+                // it does not see is walked, which gives the same result.
+                // One pass per round instead of one per survivor of the lane
+                // with the most.
+                const uint64_t bal = __ballot(mask != 0u);
+                if (bal != 0) {
+                    if (mask) {
+                        const uint32_t u = (uint32_t)__builtin_ctz(mask);
                         // Word pair (w[a], w[a+1]), a = u / 4, picked in two steps.
                         const bool up = (u & 8u) != 0, odd = (u & 4u) != 0;
                         const uint32_t p0 = up ? w[2] : w[0], p1 = up ? w[3] : w[1], p2 = up ? w[4] : w[2];
@@ -1273,6 +1291,14 @@ __device__ __forceinline__ uint64_t total_items(const ScanParams &P) {
     return BATCH ? min(P.meta[kMetaItems], P.item_cap) : (uint64_t)gridDim.x;
 }
 
+// Tiles per work item: the launch's for one text; a batch's, chosen by its
+// prep kernel once the tile count is known (clamped so that no loop can run
+// past the LDS arrays it indexes).
+template <bool BATCH>
+__device__ __forceinline__ uint64_t item_tiles(const ScanParams &P) {
+    return BATCH ? min(max(P.meta[kMetaPer], 1ull), (unsigned long long)kMaxBatchTilesPerItem) : P.tiles_per_item;
+}
+
 // Clear a work item's LDS tile counters (and hit list at stride 4).
 template <bool DEFER, bool BATCH>
 __device__ __forceinline__ void reset_item_lds(uint32_t *nm_l, uint64_t *rec_l, uint32_t *hits) {
@@ -1339,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
     }
     const WalkTabs tabs{cls, pt, tab};
 
-    const uint64_t nt = total_tiles<BATCH>(P);
+    const uint64_t nt = total_tiles<BATCH>(P), tpi = item_tiles<BATCH>(P);
     // First work item: a device ticket for a batch, the block index otherwise.
     // Later items are taken at the end of each round, before its closing
     // barrier: every thread-0 step sits between two barriers of the same
@@ -1364,11 +1390,11 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         return __builtin_amdgcn_readfirstlane(c);
     };
     for (;;) {
-        __syncthreads();
+        wg_barrier();
         const uint64_t item = item_sh;
         if (item >= total_items<BATCH>(P)) break;
-        const uint64_t tb = item * P.tiles_per_item;
-        const uint64_t te = min(nt, tb + P.tiles_per_item);
+        const uint64_t tb = item * tpi;
+        const uint64_t te = min(nt, tb + tpi);
 
         // Pipelined: once a tile's filter bits are known its bytes are dead,
         // so the next tile's loads go out before anything else.
@@ -1435,14 +1461,14 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
         if (kDefer) {
             // The rest of the list (stride 1: past what waves took while
             // streaming), shared by all waves.
-            __syncthreads();
+            wg_barrier();
             const uint32_t n = hl_count, w0 = STRIDE == 1 ? hl_walked : 0u;
             constexpr uint32_t kPer = STRIDE == 4 ? 16u : 64u;  // entries per walk batch
             for (uint32_t f = w0 + wave * kPer; f < n; f += kWaves * kPer)
                 walk_listed<BATCH, TILE, STRIDE == 4 ? 4 : 1>(P, HL, f, min(kPer, n - f), tb, tabs, nm_l, rec_l,
                                                               &item_failed);
         }
-        __syncthreads();
+        wg_barrier();
         // The item's tile results, coalesced, and its total.
         uint64_t part = 0;
         for (uint64_t k = tb + threadIdx.x; k < te; k += kBlock) {
@@ -1486,7 +1512,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
     const WalkTabs tabs{cls, nullptr};
     const uint32_t wave = wave_id();
     uint16_t *queue = reinterpret_cast<uint16_t *>(lds + Lo.ring_off()) + wave * ring_cap<STRIDE>();
-    const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P);
+    const uint64_t nt = total_tiles<BATCH>(P), items = total_items<BATCH>(P), tpi = item_tiles<BATCH>(P);
     bool staged = false, has_last = false;
     uint64_t last_total = 0;
     // Records written by earlier calls into the same output (a text matched
@@ -1497,13 +1523,13 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         any_over = 0;
     }
     ct.clear();
-    __syncthreads();
+    wg_barrier();
 
     // Thread-0 steps inside the loop sit between barriers of the same item
     // (see the scan kernel); the call's total is written after the loop.
     for (uint64_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const uint64_t tb = item * P.tiles_per_item;
-        const uint64_t te = min(nt, tb + P.tiles_per_item);
+        const uint64_t tb = item * tpi;
+        const uint64_t te = min(nt, tb + tpi);
         // Records of all earlier items, and whether any tile here overflowed.
         // A failed item (kItemFailed) fails the whole call.
         uint64_t part = 0;
@@ -1527,11 +1553,11 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             // earlier item i0: its first record follows the records of items
             // before i0 and of i0's tiles before the chunk's first tile.
             const uint64_t t0 = P.tile_start[P.tile_chunk[tb]];
-            const uint64_t i0 = t0 / P.tiles_per_item;
+            const uint64_t i0 = t0 / tpi;
             uint64_t before = 0;
             if (t0 < tb) {
                 for (uint64_t g = threadIdx.x; g < i0; g += kBlock) before += P.itemsum[g];
-                for (uint64_t t = i0 * P.tiles_per_item + threadIdx.x; t < t0; t += kBlock) before += P.tile_rec[t];
+                for (uint64_t t = i0 * tpi + threadIdx.x; t < t0; t += kBlock) before += P.tile_rec[t];
             }
             before = block_sum_u64(before, red);
             if (threadIdx.x == 0) carry_first = before;  // read after the scan's barriers below
@@ -1539,7 +1565,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         if (any_over && !staged) {
             stage_tables<FILTER>(P, bm, cls);
             staged = true;
-            __syncthreads();
+            wg_barrier();
         }
 
         for (uint64_t c0 = tb; c0 < te; c0 += kBlock) {
@@ -1550,7 +1576,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             const uint64_t tile_base = base + block_excl_scan_u64(rec, scan_sh, chunk_total);
             if (sliced && in) tile_first[t - tb] = tile_base;  // batch items fit one pass (<= kBlock tiles)
             if (threadIdx.x == 0) n_over = 0;
-            __syncthreads();
+            wg_barrier();
             // Output position of the first record of the chunk that tile t lies in.
             auto chunk_first_pos = [&](uint32_t chunk) -> uint64_t {
                 if (!sliced) return 0;
@@ -1606,7 +1632,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                     }
                 }
             }
-            __syncthreads();
+            wg_barrier();
             for (uint32_t o = wave; o < n_over; o += kWaves) {
                 const uint64_t ot = over_tile[o];
                 const TileInfo ti = tile_info<BATCH, TILE>(P, ot);
@@ -1625,7 +1651,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
                     scan_loaded_tile<STRIDE, FILTER, K, Q4, kSub>(P, ot, sub, r, bm, tabs, queue, sink);
                 }
             }
-            __syncthreads();
+            wg_barrier();
             base += chunk_total;
         }
         if (item == items - 1) {
@@ -1634,7 +1660,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
         }
         if (threadIdx.x == 0) any_over = 0;  // every read of it preceded the last barrier
         ct.flush();  // every add of the item preceded the last barrier
-        __syncthreads();
+        wg_barrier();
     }
     if (has_last && threadIdx.x == 0) {
         if (E.total) *E.total = any_failed ? ~0ull : last_total;
@@ -1659,7 +1685,7 @@ __global__ void glop_zero_kernel(uint64_t *counts, uint32_t n, uint64_t *total, 
 // total tiles and work items, a zero ticket, zero counts.  Every chunk gets at
 // least one tile, so each has a first tile to report its output position.
 template <int TILE>
-__global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P) {
+__global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P, uint32_t wgs) {
     __shared__ uint64_t sh[kWaves + 1];
     uint64_t running = 0;
     for (uint64_t c0 = 0; c0 < P.nchunks; c0 += kBlock) {
@@ -1679,7 +1705,17 @@ __global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P) {
         P.tile_start[P.nchunks] = running;
         const bool overflow = running > P.tile_cap;
         P.meta[kMetaTiles] = overflow ? 0 : running;
-        P.meta[kMetaItems] = overflow ? 0 : (running + P.tiles_per_item - 1) / P.tiles_per_item;
+        // Items of equal size in the fewest whole rounds of one item per
+        // workgroup (as for one text): each item end costs its workgroup a
+        // walk and write-out phase, and a last round with fewer items than
+        // workgroups leaves CUs idle.  At least kMinBatchTilesPerItem tiles,
+        // so the items fit the workspace's item capacity.
+        const uint64_t w = wgs ? wgs : 1;
+        const uint64_t rounds = running ? (running + w * kMaxBatchTilesPerItem - 1) / (w * kMaxBatchTilesPerItem) : 1;
+        uint64_t per = running ? (running + w * rounds - 1) / (w * rounds) : 1;
+        per = per < kMinBatchTilesPerItem ? kMinBatchTilesPerItem : per;
+        P.meta[kMetaPer] = per;
+        P.meta[kMetaItems] = overflow ? 0 : (running + per - 1) / per;
         P.meta[kMetaTicket] = 0;
         P.meta[kMetaOverflow] = overflow ? 1 : 0;
         P.meta[kMetaTotal] = 0;
@@ -1831,10 +1867,10 @@ struct Kernels {
         const size_t emit_lds = emit_dyn_lds<STRIDE, true>(P.bm_bytes);
         // Persistent workgroups: one per CU, fewer if the batch has fewer items.
         uint64_t wg = (uint64_t)(num_cus > 0 ? num_cus : 1);
-        const uint64_t items = (P.tile_cap + P.tiles_per_item - 1) / P.tiles_per_item;
+        const uint64_t items = (P.tile_cap + kMinBatchTilesPerItem - 1) / kMinBatchTilesPerItem;
         if (items < wg) wg = items ? items : 1;
         const uint32_t cus = (uint32_t)wg;
-        hipLaunchKernelGGL((glop_batch_prep_kernel<R * kRoundBytes>), dim3(1), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL((glop_batch_prep_kernel<R * kRoundBytes>), dim3(1), dim3(kBlock), 0, s, P, cus);
         hipError_t e;
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(glop_batch_map_kernel<0>, dim3(4 * cus), dim3(256), 0, s, P);

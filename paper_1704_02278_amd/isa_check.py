@@ -1,5 +1,6 @@
 """Check the gfx950 assembly of the kernels for barriers in divergent loops,
-for scratch use, and for static LDS in the scan kernels.
+for barriers not preceded by a wait for the wave's LDS operations, for
+scratch use, and for static LDS in the scan kernels.
 
 A workgroup barrier (s_barrier) is counted per wave: a wave arrives when its
 active lanes reach it.  If the compiler gives a loop that holds a barrier a
@@ -74,6 +75,38 @@ def _blocks(body):
         blocks[-1][3] = False
         blocks[-1][2].append(line)
     return [(own, note, insts) for own, note, insts, _ in blocks]
+
+
+_WAIT_LGKM0 = re.compile(r"^\s*s_waitcnt\b.*lgkmcnt\(0\)")
+_DS = re.compile(r"^\s*ds_")
+_ANY_LABEL = re.compile(r"^\S+:")
+
+
+def unwaited_barriers(body):
+    """Barriers that can be reached with the wave's LDS operations in flight.
+
+    Other waves read, right after a barrier, what this wave's LDS atomics and
+    stores wrote before it; the kernels wait for them explicitly (lgkmcnt(0))
+    just before each barrier, because the compiler's own barrier omitted that
+    wait on some paths.  Walking back from each s_barrier within its block,
+    an ``s_waitcnt ... lgkmcnt(0)`` must come before any DS instruction and
+    before the block's start.
+    """
+    bad = []
+    for i, line in enumerate(body):
+        if not _BARRIER.match(line):
+            continue
+        ok = False
+        for j in range(i - 1, -1, -1):
+            prev = body[j]
+            if _WAIT_LGKM0.match(prev):
+                ok = True
+                break
+            if _DS.match(prev) or _ANY_LABEL.match(prev):
+                break
+        if not ok:
+            bad.append(i)
+    return bad
 
 
 def check_function(body):
@@ -160,6 +193,8 @@ def check_file(path):
     out = {}
     for name, body in _functions(lines):
         p = check_function(body)
+        if "glop_" in name:
+            p += [f"s_barrier at body line {i} without a preceding lgkmcnt(0) wait" for i in unwaited_barriers(body)]
         if p:
             out[name] = p
     for name, size in scratch_sizes(lines).items():

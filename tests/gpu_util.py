@@ -91,9 +91,14 @@ def gpu_match(d: glop.Dict, text_dev: torch.Tensor, max_matches=None):
         if max_matches is not None or got <= cap:
             break
         cap = got
+    # A call that failed inside the kernels reports a total of all ones.
+    assert got >= 0, f"the call reported a failure (total {got:#x}, capacity {cap})"
     k = min(cap, got)
     o = out[:k].cpu().numpy()
-    assert np.all(out[k:].cpu().numpy() == SENTINEL), "a record was written past the total"
+    past = out[k:].cpu().numpy()
+    written = np.flatnonzero(np.any(past != SENTINEL, axis=1))
+    assert written.size == 0, (f"a record was written past the total: total {got}, capacity {cap}, "
+                               f"{written.size} rows written past it, first {past[written[:4]].tolist()}")
     return (o[:, 0].astype(np.uint64), o[:, 1].astype(np.uint64),  # the id with its zero reserved word
             counts[: d.num_patterns].cpu().numpy().astype(np.uint64), got)
 

@@ -120,3 +120,41 @@ def test_scan_kernels_must_have_no_static_lds(tmp_path):
     assert ok == {}
     bad = _check(_descriptor(scan, 0, group=16), tmp_path)
     assert bad == {scan: ["has 16 bytes of static LDS (its tables must start at address 0)"]}
+
+
+# A walk loop whose last LDS operation is an atomic add, exiting straight into
+# the barrier after which another wave reads the sum (the shape in which the
+# compiler left out the wait): the barrier must be preceded by lgkmcnt(0).
+UNWAITED = """\
+glop_scan_kernel_x:                     ; @glop_scan_kernel_x
+	s_load_dwordx2 s[0:1], s[4:5], 0x0
+.LBB0_1:                                ; =>This Inner Loop Header: Depth=1
+	ds_add_rtn_u32 v90, v15, v102
+	s_waitcnt lgkmcnt(0)
+	ds_add_u64 v14, v[54:55]
+	v_add_u32_e32 v11, 0x400, v11
+	v_cmp_ge_u32_e32 vcc, v11, v10
+	s_cbranch_vccz .LBB0_1
+.LBB0_2:
+	v_readlane_b32 s0, v112, 35
+	v_mov_b64_e32 v[10:11], 0
+	s_barrier
+	ds_read_b64 v[4:5], v37 offset:128
+	s_endpgm
+.Lfunc_end0:
+"""
+
+
+def test_flags_a_barrier_reached_with_lds_operations_in_flight(tmp_path):
+    got = _check(UNWAITED, tmp_path)
+    assert list(got) == ["glop_scan_kernel_x"]
+    (problem,) = got["glop_scan_kernel_x"]
+    assert problem.startswith("s_barrier at body line") and problem.endswith("without a preceding lgkmcnt(0) wait")
+
+
+def test_accepts_a_barrier_after_an_explicit_lds_wait(tmp_path):
+    fixed = UNWAITED.replace("\ts_barrier\n", "\ts_waitcnt lgkmcnt(0)\n\ts_barrier\n")
+    assert _check(fixed, tmp_path) == {}
+    # A DS instruction between the wait and the barrier is in flight again.
+    late = UNWAITED.replace("\ts_barrier\n", "\ts_waitcnt lgkmcnt(0)\n\tds_write_b32 v65, v37\n\ts_barrier\n")
+    assert list(_check(late, tmp_path)) == ["glop_scan_kernel_x"]
