@@ -75,7 +75,7 @@ constexpr uint32_t kPosBits = 15;
 // from a ticket, stay at 512 tiles or less (with longer ones the last items
 // left CUs idle), and at least one tile per wave.
 constexpr uint32_t kMaxTilesPerItem = 1024;
-constexpr uint32_t kMaxBatchTilesPerItem = 512;
+constexpr uint32_t kMaxBatchTilesPerItem = 1024;
 constexpr uint32_t kMinBatchTilesPerItem = 16;
 
 // A single text's split: the fewest rounds of one item per CU whose items stay
@@ -113,9 +113,9 @@ constexpr uint32_t pt_lds_cap() { return STRIDE == 4 ? 32768u : 16384u; }
 // The second filter (stride 1) uses the prefix table's room.
 static_assert((1u << GLOP_FILTER2_LOG2) / 8 <= pt_lds_cap<1>(), "second filter exceeds its LDS room");
 
-// Tile counters a work item holds in LDS: a batch's items are shorter, and
-// its kernels keep the smaller layout (sized for 1024 tiles, the batched scan
-// measured 10 % slower).
+// Tile counters a work item holds in LDS (a batch's prep kernel sizes its
+// items within the same bound: fewer item ends per workgroup measured faster
+// than items of at most 512 tiles).
 template <bool BATCH>
 constexpr uint32_t item_tiles_cap() { return BATCH ? kMaxBatchTilesPerItem : kMaxTilesPerItem; }
 
