@@ -22,7 +22,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libglop.so"
 SOURCES = ["glop_capi.cpp", "glop_trie.cpp", "glop_serve.cpp", "glop_kernels.hip"] + [
-    f"glop_kernels_{tag}.hip" for tag in "abcde"
+    f"glop_kernels_{tag}.hip" for tag in "abcdef"
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

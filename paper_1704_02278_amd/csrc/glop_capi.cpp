@@ -323,7 +323,7 @@ struct TuneRun {
     }
 
     int setup() {
-        ws_bytes = glop::workspace_bytes(len, h->num_cus);
+        ws_bytes = glop::workspace_bytes(len, h->num_cus, glop::kMinTileKiB * 1024u);  // any candidate's tiles
         cap = std::min<uint64_t>(len / 64 + 1024, 1ull << 20);
         hipError_t e;
         if ((e = hipMalloc(&ws, ws_bytes)) != hipSuccess || (e = hipMalloc((void **)&out, cap * 16)) != hipSuccess ||
@@ -572,6 +572,13 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             cand.bitmap_log2 = lg;
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
+        // Bytes per lane per tile: 4 KiB tiles (64 B per lane) where they
+        // exist, for the filter chosen so far.
+        if (cur.qgram == 4 && ((cur.stride == 4 && cur.probe_bits == 2) || (cur.stride == 1 && cur.probe_bits == 3))) {
+            glop_build_opts cand = cur;
+            cand.tile_kib = cur.tile_kib == 4 ? 8u : 4u;
+            if ((rc = consider(cand)) != GLOP_OK) return rc;
+        }
     }
     out->opts = cur;
     out->ms = best;
@@ -612,7 +619,7 @@ uint64_t glop_workspace_bytes(glop_handle_t h, uint64_t len) {
         return 0;
     }
     ok();
-    return glop::workspace_bytes(len, h->num_cus > 0 ? h->num_cus : 1);
+    return glop::workspace_bytes(len, h->num_cus > 0 ? h->num_cus : 1, h->c.tile_kib * 1024u);
 }
 
 int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
@@ -622,7 +629,7 @@ int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_mat
     if (rc != GLOP_OK) return rc;
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::workspace_bytes(len, h->num_cus);
+    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
         return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
                                      " bytes");
@@ -649,7 +656,7 @@ uint64_t glop_static_max_len(glop_handle_t h) {
     uint64_t lo = 0, hi = 1ull << 40;
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo + 1) / 2;
-        if (glop::workspace_bytes(mid, h->num_cus) <= glop::kStaticScratchBytes) lo = mid;
+        if (glop::workspace_bytes(mid, h->num_cus, h->c.tile_kib * 1024u) <= glop::kStaticScratchBytes) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -661,7 +668,7 @@ int glop_match_static(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop
     if (rc != GLOP_OK) return rc;
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::workspace_bytes(len, h->num_cus);
+    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
     if (need > glop::kStaticScratchBytes)
         return fail(GLOP_ETOOLONG, "text of " + std::to_string(len) + " bytes needs " + std::to_string(need) +
                                        " bytes of workspace; the static workspace holds " +
@@ -681,7 +688,7 @@ int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t bytes = glop::workspace_bytes(len, h->num_cus);
+    const uint64_t bytes = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
     void *ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return fail(GLOP_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
@@ -723,7 +730,7 @@ int glop_match_host(glop_handle_t h, const uint8_t *h_text, uint64_t len, glop_m
         }
     } r;
     const uint64_t buf = align256(std::max<uint64_t>(piece_max, 16));
-    const uint64_t ws_bytes = glop::workspace_bytes(piece_max, h->num_cus);
+    const uint64_t ws_bytes = glop::workspace_bytes(piece_max, h->num_cus, h->c.tile_kib * 1024u);
     const uint64_t o_ws = 2 * buf, o_cursor = o_ws + align256(ws_bytes);
     hipError_t e;
     if ((e = hipMalloc((void **)&r.dev, o_cursor + 256)) != hipSuccess)
@@ -806,7 +813,7 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
         return 0;
     }
     ok();
-    return glop::batch_workspace_bytes(nchunks, max_total_bytes);
+    return glop::batch_workspace_bytes(nchunks, max_total_bytes, h->c.tile_kib * 1024u);
 }
 
 namespace {
@@ -824,7 +831,7 @@ int match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks,
     if (max_total_bytes > (1ull << 62)) return fail(GLOP_EINVAL, "max_total_bytes too large");
     int rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes);
+    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes, h->c.tile_kib * 1024u);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
         return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
                                      " bytes");

@@ -21,11 +21,16 @@ GLOP_DECLARE_VARIANT(1, 1, 3, 0, 8)
 GLOP_DECLARE_VARIANT(1, 1, 3, 1, 8)
 GLOP_DECLARE_VARIANT(4, 1, 3, 0, 8)
 GLOP_DECLARE_VARIANT(4, 1, 3, 1, 8)
+GLOP_DECLARE_VARIANT(4, 1, 2, 1, 4)
+GLOP_DECLARE_VARIANT(1, 1, 3, 1, 4)
 
 namespace {
 
 // The Kernels<> variant that serves dictionary d.
 const VariantFns &variant_for(const GlopDevDict &d) {
+    // 4 KiB tiles exist for the two default filters (the build refuses others).
+    if (d.tile_kib == 4)
+        return d.stride == 4 ? GLOP_VARIANT_ID(4, 1, 2, 1, 4)() : GLOP_VARIANT_ID(1, 1, 3, 1, 4)();
     if (d.filter != GLOP_FILTER_QGRAM) return GLOP_VARIANT_ID(1, 0, 1, 0, 8)();
     const bool q4 = d.qgram == 4, k2 = d.probe_bits == 2;
     if (d.probe_bits == 4) return GLOP_VARIANT_ID(1, 1, 4, 1, 8)();  // stride 1, 4-byte q-grams (checked at build)
@@ -124,7 +129,9 @@ hipError_t static_scratch(int device, void **ptr) {
     return hipSuccess;
 }
 
-uint64_t workspace_bytes(uint64_t len, int num_cus) { return geometry(len, num_cus, kMinTileBytes, 15).bytes; }
+uint64_t workspace_bytes(uint64_t len, int num_cus, uint32_t tile_bytes) {
+    return geometry(len, num_cus, tile_bytes, 15).bytes;
+}
 
 uint64_t table_lds_room(int32_t filter, uint32_t stride, uint32_t bitmap_log2, uint32_t pt_lg, bool has_pt,
                         bool has_f2) {
@@ -143,8 +150,8 @@ uint64_t table_lds_room(int32_t filter, uint32_t stride, uint32_t bitmap_log2, u
     return used < kScanLdsLimit ? kScanLdsLimit - used : 0;
 }
 
-uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes) {
-    return batch_geometry(nchunks, max_total_bytes).bytes;
+uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes, uint32_t tile_bytes) {
+    return batch_geometry(nchunks, max_total_bytes, tile_bytes).bytes;
 }
 
 hipError_t prepare_kernels() {
@@ -154,7 +161,8 @@ hipError_t prepare_kernels() {
                                &GLOP_VARIANT_ID(4, 1, 1, 1, 8)(),  &GLOP_VARIANT_ID(4, 1, 2, 0, 8)(),
                                &GLOP_VARIANT_ID(4, 1, 2, 1, 8)(),  &GLOP_VARIANT_ID(1, 1, 3, 0, 8)(),
                                &GLOP_VARIANT_ID(1, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(4, 1, 3, 0, 8)(),
-                               &GLOP_VARIANT_ID(4, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(1, 1, 4, 1, 8)()};
+                               &GLOP_VARIANT_ID(4, 1, 3, 1, 8)(),   &GLOP_VARIANT_ID(1, 1, 4, 1, 8)(),
+                               &GLOP_VARIANT_ID(4, 1, 2, 1, 4)(),   &GLOP_VARIANT_ID(1, 1, 3, 1, 4)()};
     for (const VariantFns *v : all) {
         const hipError_t e = v->set_lds_limit();
         if (e != hipSuccess) return e;
@@ -196,7 +204,7 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
 
 hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     const GlopDevDict &d = a.d;
-    const BatchGeometry g = batch_geometry(a.nchunks, a.max_total_bytes);
+    const BatchGeometry g = batch_geometry(a.nchunks, a.max_total_bytes, d.tile_kib * 1024u);
     ScanParams P = base_params(d, a.counts);
     P.chunks = a.chunks;
     P.nchunks = a.nchunks;

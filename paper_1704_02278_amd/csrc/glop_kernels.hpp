@@ -45,18 +45,21 @@ struct BatchLaunch {
 };
 
 // Device workspace needed for a text of `len` bytes (any alignment).
-uint64_t workspace_bytes(uint64_t len, int num_cus);
+uint64_t workspace_bytes(uint64_t len, int num_cus, uint32_t tile_bytes);
 
 // The library's own workspace for callers that cannot allocate: a static
 // device array of kStaticScratchBytes per device.  static_scratch() gives its
 // address on `device`, which must be the current device (looked up on the
 // first call, then cached).
 constexpr uint64_t kStaticScratchBytes = 32ull << 20;
+// The smallest tile a dictionary can use (tile_kib 4): the tuner sizes its
+// workspace for it.
+constexpr uint32_t kMinTileKiB = 4;
 constexpr int kMaxDevices = 64;
 hipError_t static_scratch(int device, void **ptr);
 
 // Device workspace needed for a batch of nchunks chunks, max_total_bytes in all.
-uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes);
+uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes, uint32_t tile_bytes);
 
 // Enqueue a batch on `stream`.
 hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream);

@@ -55,7 +55,7 @@ constexpr int kWave = 64;
 constexpr int kWaves = 16;                  // waves per workgroup
 constexpr int kBlock = kWave * kWaves;      // 1024 threads
 constexpr int kRoundBytes = kWave * 16;     // 1 KiB: 16 bytes per lane
-constexpr uint32_t kMinTileBytes = 8 * kRoundBytes;
+constexpr uint32_t kMinTileBytes = 4 * kRoundBytes;  // the smallest tile (tile_kib 4)
 constexpr uint32_t kStageCap = 16;          // staged matched starts per tile
 // Per-wave LDS rings (u16 entries) for tiles walked at once.  Stride 1 queues
 // offsets half a round at a time: at most 63 left over plus 512.  Stride 4
@@ -1796,9 +1796,9 @@ struct BatchGeometry {
 };
 
 // A batch: sized for the smallest tile, so it holds either tile size.
-inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes) {
+inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes, uint32_t tile_bytes) {
     BatchGeometry g{};
-    g.tile_cap = (max_total_bytes + 16ull * nchunks) / kMinTileBytes + nchunks + 1;
+    g.tile_cap = (max_total_bytes + 16ull * nchunks) / tile_bytes + nchunks + 1;
     g.item_cap = (g.tile_cap + kMinBatchTilesPerItem - 1) / kMinBatchTilesPerItem;
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.tile_cap * 8);

@@ -277,8 +277,15 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             c.bitmap2.clear();
         }
         c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
-        if (c.tile_kib != 8) {
-            err = "tile_kib must be 0 (automatic) or 8";
+        if (c.tile_kib != 8 && c.tile_kib != 4) {
+            err = "tile_kib must be 0 (automatic), 4 or 8";
+            return GLOP_EINVAL;
+        }
+        // 4 KiB tiles exist for the two default filters only.
+        if (c.tile_kib == 4 &&
+            !(c.filter == GLOP_FILTER_QGRAM && c.qgram == 4 &&
+              ((c.stride == 4 && c.probe_bits == 2) || (c.stride == 1 && c.probe_bits == 3)))) {
+            err = "tile_kib 4 needs 4-byte q-grams with stride 4 and probe_bits 2, or stride 1 and probe_bits 3";
             return GLOP_EINVAL;
         }
     } catch (const std::bad_alloc &) {

@@ -30,7 +30,10 @@ def variants_for(patterns):
         out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, probe_bits=3))
         if minlen >= 4:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=4))
+        if minlen >= 4:
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=3, tile_kib=4))
         if minlen >= 7:
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, tile_kib=4))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=1))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=3))

@@ -246,7 +246,23 @@ def test_server_create_argument_checks():
     assert glop.glop_now_ns() >= t0 > 0
 
 
-def test_removed_tile_size_is_rejected():
+def test_tile_sizes():
     with pytest.raises(glop.GlopError):
         host_dict([b"abcdefgh"], tile_kib=16)
     assert host_dict([b"abcdefgh"], tile_kib=8).info()["tile_kib"] == 8
+    # 4 KiB tiles for the automatic filters: stride 4 with two hash bits (a
+    # shortest pattern of 7 bytes or more), stride 1 blocked (shorter ones).
+    long4 = host_dict([b"abcdefgh", b"bcdefghij"], tile_kib=4).info()
+    assert (long4["tile_kib"], long4["stride"], long4["probe_bits"]) == (4, 4, 2)
+    short4 = host_dict([b"abcd", b"bcdefghij"], tile_kib=4).info()
+    assert (short4["tile_kib"], short4["stride"], short4["probe_bits"]) == (4, 1, 3)
+    # Other filters have no 4 KiB kernels.
+    for opts in (dict(probe_bits=1), dict(stride=1, probe_bits=2), dict(filter=glop.GLOP_FILTER_NONE),
+                 dict(qgram=2, stride=1)):
+        with pytest.raises(glop.GlopError):
+            host_dict([b"abcdefgh"], tile_kib=4, **opts)
+    # The workspace holds per-tile results: twice the tiles, about twice the bytes.
+    n = 64 << 20
+    w8 = host_dict([b"abcdefgh"]).workspace_bytes(n)
+    w4 = host_dict([b"abcdefgh"], tile_kib=4).workspace_bytes(n)
+    assert 1.8 * w8 < w4 < 2.2 * w8
