@@ -93,14 +93,15 @@ typedef struct glop_dict *glop_handle_t;
  *               (stride 1, 4-byte q-grams, bitmap_log2 19 only), which lets
  *               the kernel probe two offsets per instruction on packed
  *               16-bit halves.
- *   tile_kib    0 = automatic (8), 8 or 4: KiB of text one wavefront streams
- *               per tile, 16 bytes per lane per round (8 rounds: 128 bytes
- *               per lane per tile; 4 rounds: 64).  4 exists for 4-byte
- *               q-grams with stride 4 and probe_bits 2 or stride 1 and
- *               probe_bits 3 (the automatic filters); GLOP_EINVAL otherwise.
- *               Smaller tiles give short texts more wavefronts; the
- *               workspace holds per-tile results, so glop_workspace_bytes
- *               grows with them.
+ *   tile_kib    0 = automatic, 8 or 4: KiB of text one wavefront streams
+ *               per tile in glop_match / glop_match_ws, 16 bytes per lane
+ *               per round (8 rounds: 128 bytes per lane per tile; 4 rounds:
+ *               64).  4 exists for 4-byte q-grams with stride 4 and
+ *               probe_bits 2 or stride 1 and probe_bits 3 (the automatic
+ *               filters); GLOP_EINVAL otherwise.  Automatic: 4 for stride 4
+ *               with probe_bits 2, else 8.  The workspace holds per-tile
+ *               results, so glop_workspace_bytes grows with smaller tiles.
+ *               Batches (glop_match_batch) always run 8 KiB tiles.
  *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;
  *               1..255 = the trie holds each pattern's first prefix_len bytes
  *               only (the library of Sections 2 and 5 truncates patterns to 8

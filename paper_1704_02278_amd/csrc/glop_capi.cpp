@@ -813,7 +813,7 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
         return 0;
     }
     ok();
-    return glop::batch_workspace_bytes(nchunks, max_total_bytes, h->c.tile_kib * 1024u);
+    return glop::batch_workspace_bytes(nchunks, max_total_bytes);
 }
 
 namespace {
@@ -831,7 +831,7 @@ int match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks,
     if (max_total_bytes > (1ull << 62)) return fail(GLOP_EINVAL, "max_total_bytes too large");
     int rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes, h->c.tile_kib * 1024u);
+    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
         return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
                                      " bytes");

@@ -276,7 +276,12 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
             c.bitmap.assign((1u << 12) / 32, 0);
             c.bitmap2.clear();
         }
-        c.tile_kib = o.tile_kib ? o.tile_kib : 8u;
+        // Automatic: 4 KiB tiles for stride 4 with two hash bits (the filter
+        // of dictionaries whose patterns are all 7 bytes or longer), where a
+        // single text ran 1-4 % faster with them; 8 KiB otherwise.  (Batches
+        // always run 8 KiB tiles.)
+        const bool small_tiles = c.filter == GLOP_FILTER_QGRAM && c.qgram == 4 && c.stride == 4 && c.probe_bits == 2;
+        c.tile_kib = o.tile_kib ? o.tile_kib : (small_tiles ? 4u : 8u);
         if (c.tile_kib != 8 && c.tile_kib != 4) {
             err = "tile_kib must be 0 (automatic), 4 or 8";
             return GLOP_EINVAL;

@@ -128,13 +128,13 @@ def counters_report(paths, kernel_prefix, text_bytes, kernel_us=None, cus=256, c
     out += ["", "| ratio | value |", "|---|---|"]
     tiles = text_bytes / 8192.0
     if "SQ_INSTS_VALU" in c:
-        out.append(f"| VALU wave instructions per 8 KiB tile | {c['SQ_INSTS_VALU'] / tiles:,.0f} |")
+        out.append(f"| VALU wave instructions per 8 KiB of text | {c['SQ_INSTS_VALU'] / tiles:,.0f} |")
         out.append(f"| VALU lane operations per text byte | {c['SQ_INSTS_VALU'] * 64 / text_bytes:.2f} |")
         if kernel_us:
             issue = c["SQ_INSTS_VALU"] / (cus * kernel_us * 1e-6 * clock_ghz * 1e9)
             out.append(f"| VALU issue rate (wave instructions per CU per cycle; 1 is the CU's limit) | {issue:.3f} |")
     if "SQ_INSTS_LDS" in c:
-        out.append(f"| LDS wave instructions per 8 KiB tile | {c['SQ_INSTS_LDS'] / tiles:,.0f} |")
+        out.append(f"| LDS wave instructions per 8 KiB of text | {c['SQ_INSTS_LDS'] / tiles:,.0f} |")
     if "SQ_LDS_BANK_CONFLICT" in c and c.get("SQ_INSTS_LDS"):
         out.append(f"| LDS bank-conflict cycles per LDS instruction | "
                    f"{c['SQ_LDS_BANK_CONFLICT'] / c['SQ_INSTS_LDS']:.3f} |")
@@ -143,7 +143,7 @@ def counters_report(paths, kernel_prefix, text_bytes, kernel_us=None, cus=256, c
         if tot:
             out.append(f"| L2 (TCC) hit rate | {c['TCC_HIT_sum'] / tot:.4f} |")
     if "SQ_INSTS_SALU" in c:
-        out.append(f"| SALU wave instructions per 8 KiB tile | {c['SQ_INSTS_SALU'] / tiles:,.0f} |")
+        out.append(f"| SALU wave instructions per 8 KiB of text | {c['SQ_INSTS_SALU'] / tiles:,.0f} |")
     return "\n".join(out)
 
 

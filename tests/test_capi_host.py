@@ -263,6 +263,10 @@ def test_tile_sizes():
             host_dict([b"abcdefgh"], tile_kib=4, **opts)
     # The workspace holds per-tile results: twice the tiles, about twice the bytes.
     n = 64 << 20
-    w8 = host_dict([b"abcdefgh"]).workspace_bytes(n)
+    w8 = host_dict([b"abcdefgh"], tile_kib=8).workspace_bytes(n)
     w4 = host_dict([b"abcdefgh"], tile_kib=4).workspace_bytes(n)
     assert 1.8 * w8 < w4 < 2.2 * w8
+    # Automatic: 4 KiB tiles for stride 4 with two hash bits, 8 KiB otherwise.
+    assert host_dict([b"abcdefgh", b"bcdefghij"]).info()["tile_kib"] == 4
+    assert host_dict([b"abcd", b"bcdefghij"]).info()["tile_kib"] == 8
+    assert host_dict([b"abcdefgh"], probe_bits=1).info()["tile_kib"] == 8

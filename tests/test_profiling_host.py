@@ -39,7 +39,7 @@ def test_counters_report_ratios(tmp_path):
                                   (1, SCAN, "TCC_MISS_sum", 1)])
     rep = profiling.counters_report([a], "glop_scan_kernel", text_bytes=8192 * 4, kernel_us=1.0, cus=4,
                                     clock_ghz=1.0)
-    assert "| VALU wave instructions per 8 KiB tile | 20,480 |" in rep
+    assert "| VALU wave instructions per 8 KiB of text | 20,480 |" in rep
     assert "| VALU lane operations per text byte | 160.00 |" in rep
     # 81,920 wave instructions over 4 CUs x 1,000 cycles
     assert "| VALU issue rate (wave instructions per CU per cycle; 1 is the CU's limit) | 20.480 |" in rep
