@@ -99,8 +99,13 @@ typedef struct glop_dict *glop_handle_t;
  *               64).  4 exists for 4-byte q-grams with stride 4 and
  *               probe_bits 2 or stride 1 and probe_bits 3 (the automatic
  *               filters); GLOP_EINVAL otherwise.  Automatic: 4 for stride 4
- *               with probe_bits 2, else 8.  The workspace holds per-tile
- *               results, so glop_workspace_bytes grows with smaller tiles.
+ *               with probe_bits 2; for stride 1 with probe_bits 3, 4 per call
+ *               on texts of at most 640 KiB per CU (160 MiB on 256 CUs) and
+ *               8 above; else 8.  glop_get_info reports the long-text tile.
+ *               The workspace holds per-tile results, so
+ *               glop_workspace_bytes (of the same length) grows with
+ *               smaller tiles.  glop_match_host runs every piece with the
+ *               tile of its longest piece.
  *               Batches (glop_match_batch) always run 8 KiB tiles.
  *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;
  *               1..255 = the trie holds each pattern's first prefix_len bytes

@@ -357,7 +357,9 @@ struct TuneRun {
         } else {
             o.stride = o.qgram = o.bitmap_log2 = o.probe_bits = 0;
         }
-        o.tile_kib = f.tile_kib;
+        // The tile this candidate runs on the sample (an automatic choice
+        // resolved for the sample's length, which the result then fixes).
+        o.tile_kib = f.call_tile_kib(len, hd->num_cus);
         o.prefix_len = hd->c.prefix_len ? hd->c.prefix_len : GLOP_PREFIX_FULL;
         o.candidates = 0;
         o.layout = hd->c.layout;
@@ -383,7 +385,7 @@ struct TuneRun {
         a.d.stride = f.stride;
         a.d.bitmap_log2 = f.bitmap_log2;
         a.d.probe_bits = f.probe_bits;
-        a.d.tile_kib = f.tile_kib;
+        a.d.tile_kib = o.tile_kib;
         a.text = text;
         a.len = len;
         a.out = out;
@@ -467,6 +469,7 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
     int rc = run.setup();
     if (rc != GLOP_OK) return rc;
     float best = 0.f;
+    cur.tile_kib = 0;  // automatic, resolved for the sample's length
     if ((rc = run.time(cur, &best)) != GLOP_OK) return rc;
     const float auto_ms = best;
     // Keep a candidate only if it is at least 3 % faster: smaller gains on a
@@ -563,6 +566,7 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             if (pb == pb0) continue;
             glop_build_opts cand = cur;
             cand.probe_bits = pb;
+            cand.tile_kib = 0;  // 4 KiB tiles exist for one probe count per stride
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
         const uint32_t lg0 = cur.bitmap_log2;
@@ -619,7 +623,7 @@ uint64_t glop_workspace_bytes(glop_handle_t h, uint64_t len) {
         return 0;
     }
     ok();
-    return glop::workspace_bytes(len, h->num_cus > 0 ? h->num_cus : 1, h->c.tile_kib * 1024u);
+    return glop::workspace_bytes(len, h->num_cus > 0 ? h->num_cus : 1, h->c.call_tile_kib(len, h->num_cus) * 1024u);
 }
 
 int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
@@ -629,12 +633,13 @@ int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_mat
     if (rc != GLOP_OK) return rc;
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
+    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.call_tile_kib(len, h->num_cus) * 1024u);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
         return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
                                      " bytes");
     glop::MatchLaunch a{};
     a.d = h->dd;
+    a.d.tile_kib = h->c.call_tile_kib(len, h->num_cus);
     a.text = d_text;
     a.len = len;
     a.out = d_out;
@@ -656,7 +661,7 @@ uint64_t glop_static_max_len(glop_handle_t h) {
     uint64_t lo = 0, hi = 1ull << 40;
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo + 1) / 2;
-        if (glop::workspace_bytes(mid, h->num_cus, h->c.tile_kib * 1024u) <= glop::kStaticScratchBytes) lo = mid;
+        if (glop::workspace_bytes(mid, h->num_cus, h->c.call_tile_kib(mid, h->num_cus) * 1024u) <= glop::kStaticScratchBytes) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -668,7 +673,7 @@ int glop_match_static(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop
     if (rc != GLOP_OK) return rc;
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
+    const uint64_t need = glop::workspace_bytes(len, h->num_cus, h->c.call_tile_kib(len, h->num_cus) * 1024u);
     if (need > glop::kStaticScratchBytes)
         return fail(GLOP_ETOOLONG, "text of " + std::to_string(len) + " bytes needs " + std::to_string(need) +
                                        " bytes of workspace; the static workspace holds " +
@@ -688,7 +693,7 @@ int glop_match(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_
     rc = check_device(h);
     if (rc != GLOP_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t bytes = glop::workspace_bytes(len, h->num_cus, h->c.tile_kib * 1024u);
+    const uint64_t bytes = glop::workspace_bytes(len, h->num_cus, h->c.call_tile_kib(len, h->num_cus) * 1024u);
     void *ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return fail(GLOP_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
@@ -730,7 +735,9 @@ int glop_match_host(glop_handle_t h, const uint8_t *h_text, uint64_t len, glop_m
         }
     } r;
     const uint64_t buf = align256(std::max<uint64_t>(piece_max, 16));
-    const uint64_t ws_bytes = glop::workspace_bytes(piece_max, h->num_cus, h->c.tile_kib * 1024u);
+    // Every piece runs the tile of the longest one (the workspace is sized for it).
+    const uint32_t piece_tile = h->c.call_tile_kib(piece_max, h->num_cus);
+    const uint64_t ws_bytes = glop::workspace_bytes(piece_max, h->num_cus, piece_tile * 1024u);
     const uint64_t o_ws = 2 * buf, o_cursor = o_ws + align256(ws_bytes);
     hipError_t e;
     if ((e = hipMalloc((void **)&r.dev, o_cursor + 256)) != hipSuccess)
@@ -785,6 +792,7 @@ int glop_match_host(glop_handle_t h, const uint8_t *h_text, uint64_t len, glop_m
         }
         glop::MatchLaunch a{};
         a.d = h->dd;
+        a.d.tile_kib = piece_tile;
         a.text = bytes ? dbuf : nullptr;
         a.len = bytes;
         a.out = d_out;

@@ -270,3 +270,23 @@ def test_tile_sizes():
     assert host_dict([b"abcdefgh", b"bcdefghij"]).info()["tile_kib"] == 4
     assert host_dict([b"abcd", b"bcdefghij"]).info()["tile_kib"] == 8
     assert host_dict([b"abcdefgh"], probe_bits=1).info()["tile_kib"] == 8
+
+
+def test_stride1_tile_follows_text_length():
+    # The automatic stride-1 blocked filter runs 4 KiB tiles on texts of at
+    # most 640 KiB per CU and 8 KiB above: its workspace is that of the
+    # explicit tile at each length (a host-built handle counts one CU).
+    pats = [b"abcd", b"bcdefghij"]
+    auto, t4, t8 = host_dict(pats), host_dict(pats, tile_kib=4), host_dict(pats, tile_kib=8)
+    assert (auto.info()["stride"], auto.info()["probe_bits"]) == (1, 3)
+    for n in (1, 4096, 64 << 10, 640 << 10):
+        assert auto.workspace_bytes(n) == t4.workspace_bytes(n), n
+    for n in ((640 << 10) + 1, 1 << 30, 64 << 30):
+        assert auto.workspace_bytes(n) == t8.workspace_bytes(n), n
+    # The stride-4 filter keeps 4 KiB tiles at every length.
+    long_auto, long4 = host_dict([b"abcdefgh", b"bcdefghij"]), host_dict([b"abcdefgh", b"bcdefghij"], tile_kib=4)
+    for n in (4096, 1 << 30, 64 << 30):
+        assert long_auto.workspace_bytes(n) == long4.workspace_bytes(n), n
+    # The static workspace's text limit is the last length that fits.
+    limit = int(glop.glop_static_max_len(auto.handle))
+    assert auto.workspace_bytes(limit) <= 32 << 20 < auto.workspace_bytes(limit + 1)
