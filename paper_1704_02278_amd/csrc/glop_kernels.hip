@@ -221,7 +221,7 @@ hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
     P.tile_rec = reinterpret_cast<uint64_t *>(ws + g.off_rec);
     P.tile_nm = reinterpret_cast<uint32_t *>(ws + g.off_nm);
     P.staging = reinterpret_cast<uint64_t *>(ws + g.off_stage);
-    P.tile_chunk = reinterpret_cast<uint32_t *>(ws + g.off_chunk);
+    P.tile_desc = reinterpret_cast<TileDesc *>(ws + g.off_desc);
     P.tile_start = reinterpret_cast<uint64_t *>(ws + g.off_start);
     P.itemsum = reinterpret_cast<uint64_t *>(ws + g.off_item);
     P.meta = reinterpret_cast<uint64_t *>(ws + g.off_meta);

@@ -173,6 +173,17 @@ __host__ __device__ __forceinline__ Span make_span(const uint8_t *text, uint64_t
     return s;
 }
 
+// A batch tile's chunk, written by the map kernel so that one 32-byte read
+// gives tile_info everything it needs.
+struct __align__(32) TileDesc {
+    const uint8_t *text;  // the chunk's first byte
+    uint64_t len;         // the chunk's bytes
+    uint64_t k;           // the tile's index within the chunk
+    uint32_t chunk;
+    uint32_t pad;
+};
+static_assert(sizeof(TileDesc) == 32, "TileDesc is read as eight words");
+
 struct ScanParams {
     GlopDevDict d;
     Span one;                    // single text
@@ -180,7 +191,7 @@ struct ScanParams {
     const glop_chunk_t *chunks;  // batch: chunk table
     uint32_t nchunks;
     uint64_t *tile_start;        // batch: first tile of each chunk, nchunks + 1
-    uint32_t *tile_chunk;        // batch: chunk of each tile
+    TileDesc *tile_desc;         // batch: chunk of each tile
     uint64_t *meta;              // batch: kMeta* words
     uint64_t tile_cap;           // batch: tiles the workspace holds
     uint64_t item_cap;           // batch: work items the workspace holds
@@ -618,22 +629,40 @@ struct TileInfo {
     uint32_t interior;  // 1: every byte the tile loads is inside its text
 };
 
-template <bool BATCH, int TILE>
-__device__ __forceinline__ TileInfo tile_info(const ScanParams &P, uint64_t t) {
+template <int TILE>
+__device__ __forceinline__ TileInfo tile_info_of(const Span &s, uint64_t k, uint32_t chunk) {
     TileInfo ti;
-    uint64_t k = t;
-    if (BATCH) {
-        ti.chunk = P.tile_chunk[t];
-        k = t - P.tile_start[ti.chunk];
-        const glop_chunk_t ch = P.chunks[ti.chunk];
-        ti.s = make_span(ch.text, ch.len, P.d.min_len);
-    } else {
-        ti.chunk = 0;
-        ti.s = P.one;
-    }
+    ti.s = s;
+    ti.chunk = chunk;
     ti.x0 = k * (uint64_t)TILE;
     ti.interior = (ti.x0 >= ti.s.head && ti.x0 + TILE + 4 <= ti.s.span_end) ? 1u : 0u;
     return ti;
+}
+
+template <bool BATCH, int TILE>
+__device__ __forceinline__ TileInfo tile_info(const ScanParams &P, uint64_t t) {
+    if (BATCH) {
+        const TileDesc dsc = P.tile_desc[t];
+        return tile_info_of<TILE>(make_span(dsc.text, dsc.len, P.d.min_len), dsc.k, dsc.chunk);
+    }
+    return tile_info_of<TILE>(P.one, t, 0u);
+}
+
+// A batch tile's descriptor as a vector load, lane j < 8 holding its word j.
+// It stays in flight through the current tile's probes: a scalar load would
+// be drained by their first LDS wait, which waits on scalar loads too.
+__device__ __forceinline__ uint32_t tile_desc_lanes(const ScanParams &P, uint64_t t) {
+    return reinterpret_cast<const uint32_t *>(P.tile_desc + t)[lane_id() & 7u];
+}
+
+template <int TILE>
+__device__ __forceinline__ TileInfo tile_info_lanes(const ScanParams &P, uint32_t v) {
+    uint32_t w[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) w[j] = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+    const uint8_t *text = reinterpret_cast<const uint8_t *>(((uint64_t)w[1] << 32) | w[0]);
+    const uint64_t len = ((uint64_t)w[3] << 32) | w[2], k = ((uint64_t)w[5] << 32) | w[4];
+    return tile_info_of<TILE>(make_span(text, len, P.d.min_len), k, w[6]);
 }
 
 // A wave's tile in registers: 16 bytes per lane per round, plus the first
@@ -1411,13 +1440,22 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
             const uint32_t cn = claim();
             const bool has_next = cn < ntile;
             TileInfo nxt = cur;
-            if (has_next) nxt = tile_info<BATCH, TILE>(P, tb + cn);
+            uint32_t next_desc = 0;  // batch: read once this tile's probes are done
+            if (has_next) {
+                if constexpr (BATCH) next_desc = tile_desc_lanes(P, tb + cn);
+                else nxt = tile_info<BATCH, TILE>(P, tb + cn);
+            }
+            auto load_next = [&](auto nt_loads) {
+                if (!has_next) return;
+                if constexpr (BATCH) nxt = tile_info_lanes<TILE>(P, next_desc);
+                load_tile<R, FILTER, decltype(nt_loads)::value>(nxt, r);
+            };
             StageSink sink(nm_l, rec_l, tb);
             if constexpr (STRIDE == 4) {
                 HitBits<R> pbits;
                 uint32_t xb;
                 tile_hits4<R, K, Q4>(P.d, r, bm, pbits, xb);
-                if (has_next) load_tile<R, FILTER, true>(nxt, r);
+                load_next(std::true_type{});
                 if (__ballot(pbits != 0) != 0 || xb) {
                     if (!list_hits<R>(HL, (uint32_t)(t - tb), pbits, xb))
                         walk_hits4<R>(P, t, cur, pbits, xb, tabs, queue, sink);
@@ -1427,7 +1465,7 @@ __global__ __launch_bounds__(kBlock) void glop_scan_kernel(ScanParams P) {
                 const Stage2 st2{reinterpret_cast<uint2 *>(queue),
                                  reinterpret_cast<uint32_t *>(queue) + 2 * Stage2::kEntries};
                 tile_masks1<R, FILTER, K, Q4>(P.d, cur, r, bm, 0u, bm2, m, &st2);  // bm: LDS address 0
-                if (has_next) load_tile<R, FILTER>(nxt, r);
+                load_next(std::false_type{});
                 // Survivors wait in the workgroup list, so walks run in full
                 // batches of 64 instead of one short batch per tile.  Here the
                 // probes keep the vector units busy, so a wave that finds 64
@@ -1552,7 +1590,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             // The chunk holding the item's first tile may have begun in an
             // earlier item i0: its first record follows the records of items
             // before i0 and of i0's tiles before the chunk's first tile.
-            const uint64_t t0 = P.tile_start[P.tile_chunk[tb]];
+            const uint64_t t0 = tb - P.tile_desc[tb].k;
             const uint64_t i0 = t0 / tpi;
             uint64_t before = 0;
             if (t0 < tb) {
@@ -1585,7 +1623,7 @@ __global__ __launch_bounds__(kBlock) void glop_emit_kernel(ScanParams P, EmitPar
             };
             if (in) {
                 const TileInfo ti = tile_info<BATCH, TILE>(P, t);
-                if (BATCH && t == P.tile_start[ti.chunk]) E.chunk_first[ti.chunk] = tile_base;
+                if (BATCH && ti.x0 == 0) E.chunk_first[ti.chunk] = tile_base;  // the chunk's first tile
                 const uint32_t nm = rec > 0 ? P.tile_nm[t] : 0u;
                 if (nm > kStageCap) {
                     const uint32_t slot = atomicAdd(&n_over, 1u);
@@ -1724,19 +1762,23 @@ __global__ __launch_bounds__(kBlock) void glop_batch_prep_kernel(ScanParams P, u
     for (uint32_t k = threadIdx.x; k < P.d.num_patterns; k += kBlock) P.counts[k] = 0;
 }
 
-// Batch: chunk of every tile (binary search in the first-tile table).
+// Batch: every tile's descriptor, chunk by chunk (a workgroup takes a chunk
+// and its threads its tiles).
 template <int = 0>
 __global__ void glop_batch_map_kernel(ScanParams P) {
     const uint64_t nt = min(P.meta[kMetaTiles], P.tile_cap);
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = P.nchunks;  // answer in [lo, hi)
-        while (hi - lo > 1) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            if (P.tile_start[mid] <= t) lo = mid;
-            else hi = mid;
+    for (uint32_t c = blockIdx.x; c < P.nchunks; c += gridDim.x) {
+        const uint64_t t0 = P.tile_start[c], t1 = min(P.tile_start[c + 1], nt);
+        const glop_chunk_t ch = P.chunks[c];
+        for (uint64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+            TileDesc dsc;
+            dsc.text = ch.text;
+            dsc.len = ch.len;
+            dsc.k = t - t0;
+            dsc.chunk = c;
+            dsc.pad = 0;
+            P.tile_desc[t] = dsc;
         }
-        P.tile_chunk[t] = lo;
     }
 }
 
@@ -1792,7 +1834,7 @@ inline Geometry geometry(uint64_t len, int num_cus, uint32_t tile, uint64_t head
 
 struct BatchGeometry {
     uint64_t tile_cap, item_cap;
-    uint64_t off_rec, off_nm, off_stage, off_chunk, off_start, off_item, off_meta, bytes;
+    uint64_t off_rec, off_nm, off_stage, off_desc, off_start, off_item, off_meta, bytes;
 };
 
 // A batch: sized for the smallest tile, so it holds either tile size.
@@ -1803,8 +1845,8 @@ inline BatchGeometry batch_geometry(uint32_t nchunks, uint64_t max_total_bytes, 
     g.off_rec = 0;
     g.off_nm = align256(g.off_rec + g.tile_cap * 8);
     g.off_stage = align256(g.off_nm + g.tile_cap * 4);
-    g.off_chunk = align256(g.off_stage + g.tile_cap * kStageCap * 8);
-    g.off_start = align256(g.off_chunk + g.tile_cap * 4);
+    g.off_desc = align256(g.off_stage + g.tile_cap * kStageCap * 8);
+    g.off_start = align256(g.off_desc + g.tile_cap * sizeof(TileDesc));
     g.off_item = align256(g.off_start + ((uint64_t)nchunks + 1) * 8);
     g.off_meta = align256(g.off_item + g.item_cap * 8);
     g.bytes = align256(g.off_meta + kMetaWords * 8);
