@@ -301,7 +301,8 @@ int glop_match_ws(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_mat
  * Serialise them, or use glop_match_ws with a workspace per stream.  The
  * kernels write every workspace word they later read, so nothing needs
  * clearing between calls.  A text whose workspace would exceed the array
- * (glop_static_max_len(h) bytes or more, about 1.8 GiB on 256 CUs) gives
+ * (longer than glop_static_max_len(h) bytes: about 0.9 GiB with 4 KiB tiles,
+ * 1.8 GiB with 8 KiB tiles, on 256 CUs) gives
  * GLOP_ETOOLONG before anything is enqueued.  Other errors as glop_match_ws.
  */
 int glop_match_static(glop_handle_t h, const uint8_t *d_text, uint64_t len, glop_match_t *d_out,
