@@ -106,7 +106,10 @@ typedef struct glop_dict *glop_handle_t;
  *               glop_workspace_bytes (of the same length) grows with
  *               smaller tiles.  glop_match_host runs every piece with the
  *               tile of its longest piece.
- *               Batches (glop_match_batch) always run 8 KiB tiles.
+ *               Batches (glop_match_batch) take the given tile_kib; when
+ *               automatic, 4 for a max_total_bytes of at most 64 KiB per CU
+ *               where the filter has 4 KiB kernels, else 8 (as does
+ *               glop_batch_workspace_bytes of the same max_total_bytes).
  *   prefix_len  GLOP_PREFIX_FULL = the trie holds the whole patterns;
  *               1..255 = the trie holds each pattern's first prefix_len bytes
  *               only (the library of Sections 2 and 5 truncates patterns to 8

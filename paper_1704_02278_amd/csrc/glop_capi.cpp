@@ -821,7 +821,8 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
         return 0;
     }
     ok();
-    return glop::batch_workspace_bytes(nchunks, max_total_bytes);
+    return glop::batch_workspace_bytes(nchunks, max_total_bytes,
+                                       h->c.batch_tile_kib(max_total_bytes, h->num_cus) * 1024u);
 }
 
 namespace {
@@ -839,12 +840,14 @@ int match_batch(glop_handle_t h, const glop_chunk_t *d_chunks, uint32_t nchunks,
     if (max_total_bytes > (1ull << 62)) return fail(GLOP_EINVAL, "max_total_bytes too large");
     int rc = check_device(h);
     if (rc != GLOP_OK) return rc;
-    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes);
+    const uint32_t tile_kib = h->c.batch_tile_kib(max_total_bytes, h->num_cus);
+    const uint64_t need = glop::batch_workspace_bytes(nchunks, max_total_bytes, tile_kib * 1024u);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) || workspace_bytes < need)
         return fail(GLOP_EINVAL, "workspace must be 256-byte aligned and at least " + std::to_string(need) +
                                      " bytes");
     glop::BatchLaunch a{};
     a.d = h->dd;
+    a.d.tile_kib = tile_kib;
     a.chunks = d_chunks;
     a.nchunks = nchunks;
     a.max_total_bytes = max_total_bytes;

@@ -150,8 +150,8 @@ uint64_t table_lds_room(int32_t filter, uint32_t stride, uint32_t bitmap_log2, u
     return used < kScanLdsLimit ? kScanLdsLimit - used : 0;
 }
 
-uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes) {
-    return batch_geometry(nchunks, max_total_bytes, kBatchTileKiB * 1024u).bytes;
+uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes, uint32_t tile_bytes) {
+    return batch_geometry(nchunks, max_total_bytes, tile_bytes).bytes;
 }
 
 hipError_t prepare_kernels() {
@@ -203,11 +203,8 @@ hipError_t launch_match(const MatchLaunch &a, hipStream_t stream) {
 }
 
 hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream) {
-    // A batch always runs 8 KiB tiles: with 4 KiB ones its items hold half
-    // the text and each workgroup pays twice the item ends (16 % slower on a
-    // 4,096-text batch).
-    GlopDevDict d = a.d;
-    d.tile_kib = kBatchTileKiB;
+    // a.d.tile_kib is the batch's tile (the caller sized the workspace for it).
+    const GlopDevDict &d = a.d;
     const BatchGeometry g = batch_geometry(a.nchunks, a.max_total_bytes, d.tile_kib * 1024u);
     ScanParams P = base_params(d, a.counts);
     P.chunks = a.chunks;

@@ -55,13 +55,11 @@ constexpr uint64_t kStaticScratchBytes = 32ull << 20;
 // The smallest tile a dictionary can use (tile_kib 4): the tuner sizes its
 // workspace for it.
 constexpr uint32_t kMinTileKiB = 4;
-// The tile every batch runs, whatever its dictionary's tile_kib.
-constexpr uint32_t kBatchTileKiB = 8;
 constexpr int kMaxDevices = 64;
 hipError_t static_scratch(int device, void **ptr);
 
 // Device workspace needed for a batch of nchunks chunks, max_total_bytes in all.
-uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes);
+uint64_t batch_workspace_bytes(uint32_t nchunks, uint64_t max_total_bytes, uint32_t tile_bytes);
 
 // Enqueue a batch on `stream`.
 hipError_t launch_batch(const BatchLaunch &a, hipStream_t stream);

@@ -280,12 +280,13 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
         // of dictionaries whose patterns are all 7 bytes or longer), where a
         // single text ran 1-6 % faster with them at every length; with the
         // stride-1 blocked filter, 4 KiB for short texts (kShortTextPerCu) and
-        // 8 KiB above; 8 KiB otherwise.  (Batches always run 8 KiB tiles.)
+        // 8 KiB above; 8 KiB otherwise.  (Batches: Compiled::batch_tile_kib.)
         const bool q4 = c.filter == GLOP_FILTER_QGRAM && c.qgram == 4;
         const bool small_tiles = q4 && c.stride == 4 && c.probe_bits == 2;
         const bool short_tiles = q4 && c.stride == 1 && c.probe_bits == 3;
         c.tile_kib = o.tile_kib ? o.tile_kib : (small_tiles ? 4u : 8u);
         c.tile_kib_short = !o.tile_kib && short_tiles ? 4u : 0u;
+        c.tile_auto = o.tile_kib == 0;
         if (c.tile_kib != 8 && c.tile_kib != 4) {
             err = "tile_kib must be 0 (automatic), 4 or 8";
             return GLOP_EINVAL;

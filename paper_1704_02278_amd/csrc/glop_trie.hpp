@@ -15,6 +15,10 @@ namespace glop {
 // 128 MiB 0.0842 -> 0.0821 ms); above it the longer tile keeps each lane's
 // loads in flight (256 MiB: 0.1259 vs 0.1314 ms, 4 GiB: 1.40 vs 1.63 ms).
 constexpr uint64_t kShortTextPerCu = 640ull << 10;
+// The same for a batch's byte bound, lower: a batch pays an item end per work
+// item, so halved tiles only pay on small ones (batches of 2-4 texts, 7 MB:
+// 3-5 % faster; 108 MB: 2 % slower).
+constexpr uint64_t kShortBatchPerCu = 64ull << 10;
 
 struct Compiled {
     uint32_t num_patterns = 0;
@@ -30,6 +34,7 @@ struct Compiled {
     // Automatic tile for short texts (0 = none): calls over at most
     // kShortTextPerCu bytes of text per CU run tile_kib_short KiB tiles.
     uint32_t tile_kib_short = 0;
+    bool tile_auto = true;  // tile_kib was not given
     uint64_t filter_keys = 0;
     std::vector<uint32_t> bitmap;  // 2^bitmap_log2 bits
     std::vector<uint32_t> bitmap2; // second filter, 2^GLOP_FILTER2_LOG2 bits, or empty
@@ -57,6 +62,17 @@ struct Compiled {
     uint32_t call_tile_kib(uint64_t len, int num_cus) const {
         const uint64_t cus = num_cus > 0 ? (uint64_t)num_cus : 1;
         return tile_kib_short && len <= kShortTextPerCu * cus ? tile_kib_short : tile_kib;
+    }
+    // KiB per tile for a batch of at most max_total_bytes: a given tile_kib,
+    // else 4 KiB for a short batch (kShortBatchPerCu) where the filter has
+    // 4 KiB kernels and 8 KiB for a long one (4 KiB tiles halve the text of
+    // each work item, and every item end stops its workgroup's stream: 16 %
+    // slower on 7.7 GiB).
+    uint32_t batch_tile_kib(uint64_t max_total_bytes, int num_cus) const {
+        if (!tile_auto) return tile_kib;
+        const uint64_t cus = num_cus > 0 ? (uint64_t)num_cus : 1;
+        const bool has4 = tile_kib == 4 || tile_kib_short == 4;
+        return has4 && max_total_bytes <= kShortBatchPerCu * cus ? 4u : 8u;
     }
     // The next state (with GLOP_TERM_BIT) or 0, read from the device layout.
     uint32_t step(uint32_t s, uint32_t k) const;

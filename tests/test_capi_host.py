@@ -290,3 +290,19 @@ def test_stride1_tile_follows_text_length():
     # The static workspace's text limit is the last length that fits.
     limit = int(glop.glop_static_max_len(auto.handle))
     assert auto.workspace_bytes(limit) <= 32 << 20 < auto.workspace_bytes(limit + 1)
+
+
+def test_batch_tile_follows_batch_size():
+    # Automatic dictionaries run 4 KiB batch tiles when the batch's byte bound
+    # is at most 64 KiB per CU and the filter has 4 KiB kernels, else 8 KiB; a
+    # given tile_kib holds at every size (a host-built handle counts one CU).
+    for pats in ([b"abcdefgh", b"bcdefghij"], [b"abcd", b"bcdefghij"]):
+        auto, t4, t8 = host_dict(pats), host_dict(pats, tile_kib=4), host_dict(pats, tile_kib=8)
+        for n in (1, 4096, 64 << 10):
+            assert auto.batch_workspace_bytes(3, n) == t4.batch_workspace_bytes(3, n), n
+        for n in ((64 << 10) + 1, 640 << 10, 1 << 30):
+            assert auto.batch_workspace_bytes(3, n) == t8.batch_workspace_bytes(3, n), n
+        assert t4.batch_workspace_bytes(3, 1 << 30) > 1.8 * t8.batch_workspace_bytes(3, 1 << 30)
+    # Filters without 4 KiB kernels keep 8 KiB.
+    other, other8 = host_dict([b"abcdefgh"], probe_bits=1), host_dict([b"abcdefgh"], probe_bits=1, tile_kib=8)
+    assert other.batch_workspace_bytes(3, 4096) == other8.batch_workspace_bytes(3, 4096)
