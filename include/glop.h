@@ -337,7 +337,7 @@ uint64_t glop_batch_workspace_bytes(glop_handle_t h, uint32_t nchunks, uint64_t 
 
 /*
  * Match every chunk of a batch in one persistent scan launch that takes work
- * items (runs of 8 KiB tiles, any mix of chunks) from a device work
+ * items (runs of tiles, any mix of chunks) from a device work
  * queue, then one ordered emit launch.  Everything is enqueued on `stream`
  * and reads its inputs from device memory only, so a captured hipGraph can be
  * replayed after the chunk table (and the chunks) change, as long as nchunks
@@ -604,8 +604,8 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
 /* ---- Measurement helper -----------------------------------------------------
  *
  * glop_stream_read: read the first floor(len / 16) * 16 bytes at d_data once,
- * with the scan kernel's load shape (the same split into per-workgroup items
- * of 8 KiB tiles, 16-byte coalesced non-temporal loads per lane, one tile of
+ * with the scan kernel's load shape at 8 KiB tiles (the same split into
+ * per-workgroup items of 8 KiB tiles, 16-byte coalesced non-temporal loads per lane, one tile of
  * loads in flight ahead of use) and nothing else, and fold
  * them into the device uint64_t at d_sink (its value afterwards depends on
  * every byte read and is otherwise unspecified).  Its rate is

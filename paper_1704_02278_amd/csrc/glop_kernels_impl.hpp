@@ -7,7 +7,7 @@
 // Every byte offset of the text starts a walk of the failureless trie
 // (Section 5).  The work is split in two kernels:
 //
-// scan  -- streams the text once from HBM.  Each wave owns 8 KiB tiles; a lane
+// scan  -- streams the text once from HBM.  Waves claim 4 or 8 KiB tiles; a lane
 //          holds 16 consecutive bytes per 1 KiB round (one coalesced 16-byte
 //          load).  With the q-gram filter, the lane first probes an LDS Bloom
 //          filter that summarises the trie's first q levels: an offset whose
