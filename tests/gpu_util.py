@@ -31,9 +31,13 @@ def variants_for(patterns):
         if minlen >= 4:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=4))
         if minlen >= 4:
+            # Both tile sizes of the automatic filters: short texts and small
+            # batches default to 4 KiB tiles, so 8 KiB ones are asked for.
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=3, tile_kib=4))
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=1, qgram=4, probe_bits=3, tile_kib=8))
         if minlen >= 7:
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, tile_kib=4))
+            out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, tile_kib=8))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=1))
             out.append(dict(filter=glop.GLOP_FILTER_QGRAM, stride=4, qgram=4, probe_bits=3))

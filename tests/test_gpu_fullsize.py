@@ -33,10 +33,14 @@ from gpu_util import assert_same, gpu_match, oracle_match, say, to_device  # noq
 def test_medium_full_size_bit_exact():
     pats, text, plants = synth.make_workload("medium")
     say("fullsize medium", text.size)
-    got = gpu_match(glop.Dict(pats), to_device(text))
+    dev_text = to_device(text)
+    got = gpu_match(glop.Dict(pats), dev_text)
     want = oracle_match(text, pats)
     assert want[3] >= len(plants)
     assert_same(got, want, "medium 1 GiB")
+    # The default is 4 KiB tiles here; the 8 KiB kernels at the same size.
+    say("fullsize medium, 8 KiB tiles", text.size)
+    assert_same(gpu_match(glop.Dict(pats, tile_kib=8), dev_text), want, "medium 1 GiB, 8 KiB tiles")
 
 
 def _properties(text, pats, plants, off, ids, counts, total):
