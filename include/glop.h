@@ -566,9 +566,9 @@ int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, co
  * its own hardware; here they are measured.  Starting from the automatic
  * options, the engine (whole patterns or 8-byte prefixes) and then one
  * parameter at a time is varied (filter on or off, q-gram length, stride,
- * probe bits, bitmap size) and a change is kept when it is at least 3 %
- * faster (median of 11 timed calls after 2 warm-up calls).  The sample should
- * be as large as the texts to be matched: per-call costs that do not scale
+ * probe bits, bitmap size, tile size) and a change is kept when it is at
+ * least 3 % faster (median of 11 timed calls after 2 warm-up calls).  The
+ * sample should be as large as the texts to be matched: per-call costs that do not scale
  * with the text (table staging, the end of each work item) weigh more on a
  * small one.  Every option set is exact, so all of them must report the same
  * number of matches on the sample; a difference fails the call.  The trie is
@@ -591,7 +591,8 @@ int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, co
  *         GLOP_EINTERNAL (two option sets gave different match counts).
  */
 typedef struct {
-    glop_build_opts opts; /* chosen options (all fields explicit) */
+    glop_build_opts opts; /* chosen options, all explicit but tile_kib: 0 (automatic,
+                             chosen per text length) where the automatic tile won */
     float ms;             /* median time of one match of the sample with them */
     float auto_ms;        /* the same with the automatic options */
     uint32_t evaluated;   /* option sets timed (0 when taken from the cache) */

@@ -584,6 +584,21 @@ int glop_autotune(const uint8_t *const *patterns, const uint32_t *lengths, uint3
             if ((rc = consider(cand)) != GLOP_OK) return rc;
         }
     }
+    // Where the chosen filter's automatic tile is the one that won, report it
+    // as automatic, so that texts of other lengths still get their own tile.
+    if (cur.filter == GLOP_FILTER_QGRAM) {
+        glop_build_opts a = cur;
+        a.tile_kib = 0;
+        glop::Compiled f;
+        f.min_len = run.h->c.min_len;
+        f.num_patterns = n;
+        std::string err;
+        if (glop::build_filter(patterns, n, a, f, err) == GLOP_OK &&
+            f.call_tile_kib(sample_len, run.h->num_cus) == cur.tile_kib)
+            cur.tile_kib = 0;
+    } else if (cur.tile_kib == 8) {
+        cur.tile_kib = 0;  // the only tile without the filter
+    }
     out->opts = cur;
     out->ms = best;
     out->auto_ms = auto_ms;
