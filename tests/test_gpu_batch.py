@@ -50,7 +50,8 @@ def _check_batch(d, pats, pieces, chunks, res):
 
 
 def _mixed_pieces(text, rng, n):
-    sizes = [0, 1, 3, 7, 8, 8191, 8192, 8193, 16383, 16384, 16385, 1 << 16]
+    # Around both tile sizes (small batches run 4 KiB tiles, larger ones 8 KiB).
+    sizes = [0, 1, 3, 7, 8, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16384, 16385, 1 << 16]
     sizes += [int(x) for x in np.exp(rng.uniform(0, np.log(300_000), size=n - len(sizes)))]
     pieces, pos = [], 0
     for s in sizes:
