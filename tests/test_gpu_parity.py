@@ -106,12 +106,14 @@ def test_unaligned_text_and_ragged_lengths():
             assert_same(gpu_match(d, to_device(sub, shift=shift)), oracle_match(sub, pats), f"shift {shift} n {n}")
 
 
-def test_tile_boundary_straddles():
-    # One plant per 8 KiB tile, at every offset from 40 bytes before to 8 after
-    # the tile's end, so occurrences straddle wave-tile and round boundaries.
+@pytest.mark.parametrize("tile,short", [(8192, (b"HIS", b"ISTO")), (4096, (b"ISTO",)), (4096, ())])
+def test_tile_boundary_straddles(tile, short):
+    # One plant per tile, at every offset from 40 bytes before to 8 after the
+    # tile's end, so occurrences straddle wave-tile and round boundaries.  The
+    # 4 KiB cases have a shortest pattern of 4 bytes (stride 1) or 26 (stride
+    # 4): the filters whose short texts run 4 KiB tiles by default.
     rng = np.random.default_rng(7)
-    tile = 8192
-    pats = [b"HISTORY-of-a-long-pattern-" + bytes([65 + k]) * (k + 1) for k in range(6)] + [b"HIS", b"ISTO"]
+    pats = [b"HISTORY-of-a-long-pattern-" + bytes([65 + k]) * (k + 1) for k in range(6)] + list(short)
     deltas = list(range(-40, 9))
     text = rng.integers(0x61, 0x7B, size=tile * (len(deltas) + 2), dtype=np.uint8)
     for m, dlt in enumerate(deltas, start=1):
@@ -121,7 +123,7 @@ def test_tile_boundary_straddles():
     want = oracle_match(text, pats)
     for shift in (0, 5, 13):
         for opts in variants_for(pats):
-            say("straddle", shift, opts)
+            say("straddle", tile, len(short), shift, opts)
             d = build_variant(pats, opts)
             if d is not None:
                 assert_same(gpu_match(d, to_device(text, shift=shift)), want, f"{opts}")
