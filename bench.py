@@ -140,7 +140,7 @@ def cpu_trie_baseline(d, text: np.ndarray, target_s: float) -> dict:
         d.cpu_walk(text[:n], threads=thr, max_matches=0)
         dt = time.perf_counter() - t0
         out[f"threads_{thr}"] = {"value": round(n / dt / 1e9, 6), "unit": "GB/s", "bytes": n}
-    return {"kind": "failureless-trie walk on the host (the paper's CPU counterpart)", **out}
+    return {"kind": "failureless-trie walk on the host (the CPU side of the paper's comparison)", **out}
 
 
 def bench_host_stream(d, text: np.ndarray, reps: int = 3, chunk_bytes: int = 64 << 20) -> dict:

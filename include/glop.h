@@ -394,7 +394,7 @@ int glop_match_batch_sliced(glop_handle_t h, const glop_chunk_t *d_chunks, uint3
 
 /*
  * The failureless-trie walk on the host CPU over the same compiled trie (the
- * CPU counterpart the paper measures in Section 7).  A timing baseline and a
+ * CPU side of the comparison in Section 7).  A timing baseline and a
  * check of the trie compiler; glop_match never calls it.
  *
  *   text         host pointer to len bytes.
