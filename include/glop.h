@@ -428,7 +428,7 @@ typedef struct {
     uint32_t prefix_slots;   /* slots of the prefix table (a power of two, or 0) */
     uint32_t prefix_depth;   /* 8 if every pattern is at least 8 bytes, else 4 (or 0) */
     uint32_t filter2_log2;   /* bits (log2) of the second filter checked before
-                                stride-1 walks (three bits per key), or 0 when
+                                stride-1 walks (five bits per key), or 0 when
                                 there is none */
     uint32_t layout;         /* GLOP_LAYOUT_DENSE or GLOP_LAYOUT_HYBRID as chosen */
     uint32_t placement;      /* GLOP_PLACE_GLOBAL or GLOP_PLACE_LDS as chosen

@@ -1062,13 +1062,14 @@ __device__ __forceinline__ bool list_offsets1(const HitList &L, uint32_t t_rel, 
 // Bit u of round k's 16-bit mask (word k/2, half k%2) marks offset
 // x0 + k*1024 + lane*16 + u as not ruled out.
 
-// The second filter's three bits for key g (double hashing: the top bits of h,
-// k and h + k); bit 0 of the result is 1 if all three are set.
+// The second filter's five bits for key g (double hashing: the top bits of h,
+// k, h + k, h + 2k and h + 3k); bit 0 of the result is 1 if all five are set.
 __device__ __forceinline__ uint32_t filter2_bits(const uint32_t *bm2, uint32_t g) {
-    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h), hk = h + k;
+    const uint32_t h = glop_hash2(g), k = glop_f2_mix(h), hk = h + k, h2 = hk + k, h3 = h2 + k;
     constexpr uint32_t sh2 = 32u - GLOP_FILTER2_LOG2;
     return (bm2[h >> (sh2 + 5u)] >> ((h >> sh2) & 31u)) & (bm2[k >> (sh2 + 5u)] >> ((k >> sh2) & 31u)) &
-           (bm2[hk >> (sh2 + 5u)] >> ((hk >> sh2) & 31u));
+           (bm2[hk >> (sh2 + 5u)] >> ((hk >> sh2) & 31u)) & (bm2[h2 >> (sh2 + 5u)] >> ((h2 >> sh2) & 31u)) &
+           (bm2[h3 >> (sh2 + 5u)] >> ((h3 >> sh2) & 31u));
 }
 
 // Per-wave staging of the second filter (stride 1), in the wave's LDS ring,

@@ -258,7 +258,7 @@ int build_filter(const uint8_t *const *patterns, uint32_t n, const glop_build_op
                 c.bitmap2.assign((1u << GLOP_FILTER2_LOG2) / 32, 0u);
                 for (uint32_t g : keys) {
                     const uint32_t h = glop_hash2(g), k = glop_f2_mix(h);
-                    for (uint32_t x : {h, k, h + k}) {
+                    for (uint32_t x : {h, k, h + k, h + 2u * k, h + 3u * k}) {
                         const uint32_t s2 = x >> (32u - GLOP_FILTER2_LOG2);
                         c.bitmap2[s2 >> 5] |= 1u << (s2 & 31);
                     }
