@@ -567,7 +567,8 @@ int glop_server_run_trace(glop_server_t s, uint32_t n, const uint32_t *dicts, co
  * options, the engine (whole patterns or 8-byte prefixes) and then one
  * parameter at a time is varied (filter on or off, q-gram length, stride,
  * probe bits, bitmap size, tile size) and a change is kept when it is at
- * least 3 % faster (median of 11 timed calls after 2 warm-up calls).  The
+ * least 3 % faster (median of 11 timed calls after 2 warm-up calls, and
+ * after 50 ms of settling calls before the first candidate).  The
  * sample should be as large as the texts to be matched: per-call costs that do not scale
  * with the text (table staging, the end of each work item) weigh more on a
  * small one.  Every option set is exact, so all of them must report the same
